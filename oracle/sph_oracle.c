@@ -1,0 +1,709 @@
+/*
+ * FP64 CPU oracle for the semi-implicit SPH viscous solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this code.  It shares no source with the
+ * HIP library: it is a plain, slow, directly readable transcription of what
+ * the paper defines, compiled with contraction off (-ffp-contract=off) so
+ * every product is rounded on its own, as the paper's appendix on symmetry
+ * pitfalls (fused multiply-add) requires.
+ *
+ * Contents, each citing the passage it follows:
+ *   - Wendland psi_{3,1} kernel w(q), f(q)       Section "Smoothing kernel choice"
+ *   - neighbour sets: brute force and a cell grid Section "Smoothing kernel choice"
+ *                                                 (support radius 2h), appendix on
+ *                                                 relative positions (minimum image)
+ *   - the viscous matrix A(dt), matrix-free and dense
+ *                                                 eqs. kab, implicit-system-base, diag,
+ *                                                 offdiag, implicit-system-dummy-full
+ *   - Jacobi scaling                              appendix "Implementation notes"
+ *   - robust (restructured) BiCGSTAB and the textbook BiCGSTAB, three systems
+ *     sharing one matrix, with the three-state stopping rule
+ *                                                 Section "Restructuring the stabilized
+ *                                                 biconjugate gradient method"
+ *
+ * Readings of passages that are ambiguous or inconsistent in the paper:
+ *   - Sign of K (eq. kab): the Wendland F is <= 0, so the printed K would be
+ *     >= 0 and the printed diagonal 1 - dt sum K could not be strictly
+ *     diagonally dominant, contradicting the paper's own claim.  We take the
+ *     physically diffusive reading: pair weight w = -2 mubar m_a F/(rho_a rho_b)
+ *     >= 0, A_bb = 1 + dt sum w, A_ba = -dt w (i.e. K = -w in eqs. diag/offdiag).
+ *   - tau^2 floor: "lower bound" -> tau^2 = max(eps^2 b.b, floor).
+ *   - gamma_1 = r0.r0 for the first iteration of the robust variant.
+ *   - a zero or non-finite delta, omega or gamma' marks the component stalled
+ *     and zeroes the dependent coefficients; the iteration still completes.
+ *   - converged components keep iterating while any component progresses;
+ *     "converged" takes precedence over "stalled" in the state.
+ *   - convergence is checked before the first iteration (0 iterations when
+ *     every component already meets its threshold).
+ *   - true residual: every `true_res_period` iterations and whenever no
+ *     component is progressing, r_true = b - A x is recomputed; a component
+ *     marked converged whose true residual fails the threshold is restarted
+ *     from r_true (r0hat = r_true, alpha' = beta = 0) and made progressing.
+ *   - textbook variant: when the half-step residual s already meets the
+ *     threshold the component takes omega = 0 (x = x + alpha p, r = s).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_FLUID 0
+#define ORC_WALL 1
+#define ORC_WALL_DYNAMIC 0
+#define ORC_WALL_DUMMY 1
+#define ORC_AVG_ARITH 0
+#define ORC_AVG_HARMONIC 1
+
+#define ORC_CONVERGED 0
+#define ORC_STALLED 1
+#define ORC_PROGRESSING 2
+
+#define ORC_OK 0
+#define ORC_STATUS_STALLED 1
+#define ORC_NOT_CONVERGED 2
+#define ORC_E_ARG (-1)
+#define ORC_E_NONFINITE (-5)
+
+static const double ORC_PI = 3.14159265358979323846;
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wendland psi_{3,1} kernel, radius 2 (Section "Smoothing kernel choice"):   */
+/*   W(r,h) = w(r/h)/h^3,  w(q) = 21/(16 pi) (1 - q/2)^4 (2q + 1),  q <= 2     */
+/*   F(r,h) = f(r/h)/h^5,  f(q) = 105/(128 pi) (q - 2)^3,           q <= 2     */
+/* with F = (1/r) dW/dr (Section "Spatial discretization").                  */
+/* ------------------------------------------------------------------------ */
+double orc_wendland_w(double q) {
+    if (!(q < 2.0)) return 0.0;
+    double a = 1.0 - 0.5 * q;
+    return 21.0 / (16.0 * ORC_PI) * (a * a * a * a) * (2.0 * q + 1.0);
+}
+
+double orc_wendland_f(double q) {
+    if (!(q < 2.0)) return 0.0;
+    double a = q - 2.0;
+    return 105.0 / (128.0 * ORC_PI) * (a * a * a);
+}
+
+/* Displacement r_i - r_j on one axis, minimum image when the axis is periodic. */
+static double orc_disp(double xi, double xj, double period) {
+    double d = xi - xj;
+    if (period > 0.0) {
+        double k = nearbyint(d / period);
+        d = d - period * k;
+    }
+    return d;
+}
+
+/* Squared distance, summed as (dx^2 + dy^2) + dz^2. */
+static double orc_dist2(const double *x, const double *y, const double *z, int64_t i, int64_t j,
+                        const double period[3], double *dx, double *dy, double *dz) {
+    double a = orc_disp(x[i], x[j], period[0]);
+    double b = orc_disp(y[i], y[j], period[1]);
+    double c = orc_disp(z[i], z[j], period[2]);
+    if (dx) { *dx = a; *dy = b; *dz = c; }
+    return (a * a + b * b) + c * c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour sets N(i) = { j != i : |r_i - r_j|^2 < (2h)^2 }.                  */
+/* CSR by row, columns ascending.  Returns total nnz; cols is written only     */
+/* up to `cap` entries (the caller re-calls with enough room).                */
+/* ------------------------------------------------------------------------ */
+int64_t orc_neighbors_brute(int64_t n, const double *x, const double *y, const double *z,
+                            const double *period, double h, int64_t *row_ptr, int32_t *cols,
+                            int64_t cap) {
+    double s = 2.0 * h;
+    double cut2 = s * s;
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) ++c;
+        cnt[i] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    int64_t nnz = row_ptr[n];
+    if (nnz <= cap) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t k = row_ptr[i];
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) cols[k++] = (int32_t)j;
+        }
+    }
+    free(cnt);
+    return nnz;
+}
+
+static int orc_cmp_i32(const void *a, const void *b) {
+    int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+    return (u > v) - (u < v);
+}
+
+/* Cell-grid search: particles are binned into cells no smaller than 2h along
+ * each axis (the bounding box of the data on non-periodic axes, the period on
+ * periodic ones); each particle tests the particles of the (deduplicated)
+ * 3x3x3 block of cells around its own.  Same predicate as the brute force. */
+typedef struct {
+    int nc[3];
+    double org[3], cs[3];
+    int64_t *start; /* [ncell + 1] */
+    int64_t *items; /* particle ids grouped by cell, ascending inside a cell */
+    int32_t *cell_of;
+} orc_grid;
+
+static int orc_cell_axis(double v, double org, double cs, int nc, int periodic) {
+    double u = floor((v - org) / cs);
+    long c = (long)u;
+    if (periodic) {
+        c %= nc;
+        if (c < 0) c += nc;
+    } else {
+        if (c < 0) c = 0;
+        if (c >= nc) c = nc - 1;
+    }
+    return (int)c;
+}
+
+static void orc_grid_build(orc_grid *g, int64_t n, const double *x, const double *y,
+                           const double *z, const double *lo, const double *period, double h) {
+    const double *p[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) {
+        double ext;
+        if (period[a] > 0.0) {
+            g->org[a] = lo[a];
+            ext = period[a];
+        } else {
+            double mn = p[a][0], mx = p[a][0];
+            for (int64_t i = 1; i < n; ++i) {
+                if (p[a][i] < mn) mn = p[a][i];
+                if (p[a][i] > mx) mx = p[a][i];
+            }
+            g->org[a] = mn;
+            ext = mx - mn;
+        }
+        int nc = (int)floor(ext / (2.0 * h));
+        if (nc < 1) nc = 1;
+        if (period[a] <= 0.0 && ext <= 0.0) ext = 1.0;
+        g->nc[a] = nc;
+        g->cs[a] = ext / nc;
+        if (period[a] <= 0.0 && nc == 1) g->cs[a] = ext > 0.0 ? ext * 2.0 : 1.0;
+    }
+    int64_t ncell = (int64_t)g->nc[0] * g->nc[1] * g->nc[2];
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->items = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    g->cell_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int c0 = orc_cell_axis(x[i], g->org[0], g->cs[0], g->nc[0], period[0] > 0.0);
+        int c1 = orc_cell_axis(y[i], g->org[1], g->cs[1], g->nc[1], period[1] > 0.0);
+        int c2 = orc_cell_axis(z[i], g->org[2], g->cs[2], g->nc[2], period[2] > 0.0);
+        int64_t c = ((int64_t)c2 * g->nc[1] + c1) * g->nc[0] + c0;
+        g->cell_of[i] = (int32_t)c;
+        g->start[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)calloc((size_t)ncell, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) { /* ascending i => ascending inside each cell */
+        int64_t c = g->cell_of[i];
+        g->items[g->start[c] + fill[c]++] = i;
+    }
+    free(fill);
+}
+
+static void orc_grid_free(orc_grid *g) {
+    free(g->start);
+    free(g->items);
+    free(g->cell_of);
+}
+
+/* Distinct neighbour cells of cell c (at most 27). */
+static int orc_grid_stencil(const orc_grid *g, int64_t c, const double *period, int64_t *out) {
+    int cc[3];
+    cc[0] = (int)(c % g->nc[0]);
+    cc[1] = (int)((c / g->nc[0]) % g->nc[1]);
+    cc[2] = (int)(c / ((int64_t)g->nc[0] * g->nc[1]));
+    int m = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int d[3] = {dx, dy, dz}, q[3], ok = 1;
+                for (int a = 0; a < 3; ++a) {
+                    q[a] = cc[a] + d[a];
+                    if (period[a] > 0.0) {
+                        q[a] %= g->nc[a];
+                        if (q[a] < 0) q[a] += g->nc[a];
+                    } else if (q[a] < 0 || q[a] >= g->nc[a]) {
+                        ok = 0;
+                    }
+                }
+                if (!ok) continue;
+                int64_t id = ((int64_t)q[2] * g->nc[1] + q[1]) * g->nc[0] + q[0];
+                int dup = 0;
+                for (int k = 0; k < m; ++k) dup |= (out[k] == id);
+                if (!dup) out[m++] = id;
+            }
+    return m;
+}
+
+int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y, const double *z,
+                           const double *lo, const double *period, double h, int64_t *row_ptr,
+                           int32_t *cols, int64_t cap) {
+    orc_grid g;
+    orc_grid_build(&g, n, x, y, z, lo, period, h);
+    double s = 2.0 * h;
+    double cut2 = s * s;
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t st[27];
+        int m = orc_grid_stencil(&g, g.cell_of[i], period, st);
+        int64_t c = 0;
+        for (int k = 0; k < m; ++k)
+            for (int64_t t = g.start[st[k]]; t < g.start[st[k] + 1]; ++t) {
+                int64_t j = g.items[t];
+                if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) ++c;
+            }
+        cnt[i] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    int64_t nnz = row_ptr[n];
+    if (nnz <= cap) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t st[27];
+            int m = orc_grid_stencil(&g, g.cell_of[i], period, st);
+            int64_t k0 = row_ptr[i], k = k0;
+            for (int q = 0; q < m; ++q)
+                for (int64_t t = g.start[st[q]]; t < g.start[st[q] + 1]; ++t) {
+                    int64_t j = g.items[t];
+                    if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) cols[k++] = (int32_t)j;
+                }
+            qsort(cols + k0, (size_t)(k - k0), sizeof(int32_t), orc_cmp_i32);
+        }
+    }
+    free(cnt);
+    orc_grid_free(&g);
+    return nnz;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The viscous matrix A(dt) (Section "From explicit to semi-implicit").       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr;
+    const int32_t *cols;
+    const double *x, *y, *z;
+    double period[3];
+    double h;
+    const double *mass, *rho, *mu;
+    const uint8_t *type;
+    double dt;
+    int32_t wall;   /* ORC_WALL_DYNAMIC / ORC_WALL_DUMMY */
+    int32_t avg;    /* ORC_AVG_ARITH / ORC_AVG_HARMONIC */
+    int32_t jacobi; /* 1: rows scaled by 1/A_bb (appendix "Implementation notes") */
+} orc_op;
+
+/* 2 * mubar_ab: arithmetic mean (mu_a + mu_b)/2 or harmonic 2 mu_a mu_b/(mu_a + mu_b)
+ * (Section "Discretized equations"). */
+static double orc_two_mubar(double ma, double mb, int avg) {
+    if (avg == ORC_AVG_HARMONIC) {
+        double s = ma + mb;
+        return s > 0.0 ? 4.0 * (ma * mb) / s : 0.0;
+    }
+    return ma + mb;
+}
+
+/* Pair weight w_ba = -2 mubar_ab m_a F_ab / (rho_a rho_b) >= 0 for row b and
+ * neighbour a (eq. kab with the diffusive sign reading). */
+static double orc_pair_w(const orc_op *op, int64_t b, int64_t a) {
+    double r2 = orc_dist2(op->x, op->y, op->z, b, a, op->period, 0, 0, 0);
+    double q = sqrt(r2) / op->h;
+    double h2 = op->h * op->h;
+    double F = orc_wendland_f(q) / (h2 * h2 * op->h);
+    double tm = orc_two_mubar(op->mu[a], op->mu[b], op->avg);
+    return -(tm * op->mass[a] * F) / (op->rho[a] * op->rho[b]);
+}
+
+/* Kernel value W_ba used by the dummy-wall rows (eq. dummyvel). */
+static double orc_pair_W(const orc_op *op, int64_t b, int64_t a) {
+    double r2 = orc_dist2(op->x, op->y, op->z, b, a, op->period, 0, 0, 0);
+    double q = sqrt(r2) / op->h;
+    return orc_wendland_w(q) / (op->h * op->h * op->h);
+}
+
+/* Diagonal A_bb: 1 + dt sum_a w_ba for fluid rows (eq. diag), 1 for wall rows. */
+static double orc_row_diag(const orc_op *op, int64_t b) {
+    if (op->type[b] != ORC_FLUID) return 1.0;
+    double sw = 0.0;
+    for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) sw += orc_pair_w(op, b, op->cols[k]);
+    return 1.0 + op->dt * sw;
+}
+
+void orc_diag(const orc_op *op, double *d) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < op->n; ++b) d[b] = orc_row_diag(op, b);
+}
+
+/* y = A x (or D^-1 A x with Jacobi) for the three components, matrix-free.
+ *   fluid row b:        y_b = (1 + dt sum w_ba) x_b - dt sum w_ba x_a   (eq. implicit-system-base)
+ *   dynamic wall row b: y_b = x_b                                       (eq. implicit-system-dyn-full)
+ *   dummy wall row b:   y_b = x_b + sum_{a in F} W_ba x_a / sum_{a in F} W_ba
+ *                       (identity when no fluid neighbour)              (eq. implicit-system-dummy-full) */
+void orc_apply(const orc_op *op, const double *const *xin, double *const *yout) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < op->n; ++b) {
+        double y0, y1, y2;
+        if (op->type[b] == ORC_FLUID) {
+            double sw = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                int64_t a = op->cols[k];
+                double w = orc_pair_w(op, b, a);
+                sw += w;
+                s0 += w * xin[0][a];
+                s1 += w * xin[1][a];
+                s2 += w * xin[2][a];
+            }
+            double diag = 1.0 + op->dt * sw;
+            y0 = diag * xin[0][b] - op->dt * s0;
+            y1 = diag * xin[1][b] - op->dt * s1;
+            y2 = diag * xin[2][b] - op->dt * s2;
+            if (op->jacobi) {
+                y0 /= diag;
+                y1 /= diag;
+                y2 /= diag;
+            }
+        } else if (op->wall == ORC_WALL_DUMMY) {
+            double sW = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                int64_t a = op->cols[k];
+                if (op->type[a] != ORC_FLUID) continue;
+                double W = orc_pair_W(op, b, a);
+                sW += W;
+                s0 += W * xin[0][a];
+                s1 += W * xin[1][a];
+                s2 += W * xin[2][a];
+            }
+            y0 = xin[0][b];
+            y1 = xin[1][b];
+            y2 = xin[2][b];
+            if (sW > 0.0) {
+                y0 += s0 / sW;
+                y1 += s1 / sW;
+                y2 += s2 / sW;
+            }
+        } else {
+            y0 = xin[0][b];
+            y1 = xin[1][b];
+            y2 = xin[2][b];
+        }
+        yout[0][b] = y0;
+        yout[1][b] = y1;
+        yout[2][b] = y2;
+    }
+}
+
+/* Dense row-major n x n assembly of A (or D^-1 A), entry by entry from eqs.
+ * diag / offdiag and the dummy-wall row. */
+void orc_assemble_dense(const orc_op *op, double *A) {
+    int64_t n = op->n;
+    memset(A, 0, sizeof(double) * (size_t)(n * n));
+    for (int64_t b = 0; b < n; ++b) {
+        double *row = A + b * n;
+        if (op->type[b] == ORC_FLUID) {
+            double diag = orc_row_diag(op, b);
+            double scale = op->jacobi ? 1.0 / diag : 1.0;
+            row[b] = op->jacobi ? 1.0 : diag;
+            for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                int64_t a = op->cols[k];
+                row[a] += -op->dt * orc_pair_w(op, b, a) * scale;
+            }
+        } else if (op->wall == ORC_WALL_DUMMY) {
+            double sW = 0.0;
+            for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                int64_t a = op->cols[k];
+                if (op->type[a] == ORC_FLUID) sW += orc_pair_W(op, b, a);
+            }
+            row[b] = 1.0;
+            if (sW > 0.0)
+                for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                    int64_t a = op->cols[k];
+                    if (op->type[a] == ORC_FLUID) row[a] += orc_pair_W(op, b, a) / sW;
+                }
+        } else {
+            row[b] = 1.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* BiCGSTAB for d = 3 systems sharing one matrix.                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t iters;
+    int32_t status;
+    int32_t state[3];
+    int32_t stall_count[3];
+    double rr[3];       /* final recursive r.r (scaled system) */
+    double bb[3];       /* b.b of the scaled right-hand side */
+    double tau2[3];
+    double true_rr[3];  /* final (b - A x).(b - A x) of the scaled system */
+    int32_t n_true_checks;
+    int32_t n_replaced;
+    int32_t history_len;
+} orc_report;
+
+#define ORC_ROBUST 0
+#define ORC_STANDARD 1
+
+static double orc_dot(int64_t n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+static int orc_finite(double v) { return isfinite(v); }
+
+/* r = bh - Ah x for all three components. */
+static void orc_residual(const orc_op *op, double *const *bh, double *const *x, double *const *r,
+                         double *const *tmp) {
+    orc_apply(op, (const double *const *)x, tmp);
+    for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < op->n; ++i) r[c][i] = bh[c][i] - tmp[c][i];
+}
+
+/*
+ * Solve A V = B for the three columns of B.  With op->jacobi the system is
+ * left-scaled: Ah = D^-1 A, bh = D^-1 b (appendix "Implementation notes"),
+ * and every threshold refers to the scaled residual.
+ *
+ * b, x: three component arrays of length n; x holds the initial guess on
+ * entry and the solution on exit.  history (optional) receives r.r per
+ * component at the end of every iteration, history[3*it + c], it = 0 being
+ * the initial residual.
+ *
+ * force_stall_iter / force_stall_comp: host-forced breakdown used by the
+ * failure-handling tests -- at that iteration that component's delta is
+ * treated as zero.  Pass -1 to disable.
+ */
+int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, double *const *x,
+                 double tol, int32_t max_iter, double floor_, int32_t true_res_period,
+                 int32_t force_stall_iter, int32_t force_stall_comp, orc_report *rep,
+                 double *history, int32_t history_cap) {
+    int64_t n = op->n;
+    memset(rep, 0, sizeof(*rep));
+    double *buf = (double *)calloc((size_t)(n > 0 ? n : 1) * 3 * 9, sizeof(double));
+    double *bh[3], *r[3], *rh0[3], *p[3], *Ap[3], *s[3], *As[3], *tmp[3], *D[3];
+    for (int c = 0; c < 3; ++c) {
+        bh[c] = buf + (0 * 3 + c) * n;
+        r[c] = buf + (1 * 3 + c) * n;
+        rh0[c] = buf + (2 * 3 + c) * n;
+        p[c] = buf + (3 * 3 + c) * n;
+        Ap[c] = buf + (4 * 3 + c) * n;
+        s[c] = buf + (5 * 3 + c) * n;
+        As[c] = buf + (6 * 3 + c) * n;
+        tmp[c] = buf + (7 * 3 + c) * n;
+        D[c] = buf + (8 * 3 + c) * n;
+    }
+    /* Jacobi: D = diag(A); bh = b / D. */
+    if (op->jacobi) orc_diag(op, D[0]);
+    for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < n; ++i) bh[c][i] = op->jacobi ? b[c][i] / D[0][i] : b[c][i];
+
+    double gamma[3], gamma_prev[3], alpha[3], alphap[3], beta[3], omega[3], delta[3], tau2[3], rr[3];
+    int state[3];
+    for (int c = 0; c < 3; ++c) {
+        rep->bb[c] = orc_dot(n, bh[c], bh[c]);
+        if (!orc_finite(rep->bb[c])) {
+            free(buf);
+            rep->status = ORC_E_NONFINITE;
+            return ORC_E_NONFINITE;
+        }
+    }
+    /* r0 = bh - Ah x0; r0hat = r0; tau^2 = max(eps^2 bh.bh, floor). */
+    orc_residual(op, bh, x, r, tmp);
+    int hl = 0;
+    for (int c = 0; c < 3; ++c) {
+        memcpy(rh0[c], r[c], sizeof(double) * (size_t)n);
+        tau2[c] = tol * tol * rep->bb[c];
+        if (tau2[c] < floor_) tau2[c] = floor_;
+        rr[c] = orc_dot(n, r[c], r[c]);
+        gamma[c] = orc_dot(n, rh0[c], r[c]);
+        alphap[c] = 0.0;
+        beta[c] = 0.0;
+        /* textbook start: gamma_0 = alpha_0 = omega_0 = 1, p_0 = v_0 = 0 */
+        gamma_prev[c] = 1.0;
+        alpha[c] = 1.0;
+        omega[c] = 1.0;
+        delta[c] = 0.0;
+        state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+        if (history && hl < history_cap) history[3 * hl + c] = rr[c];
+    }
+    hl = 1;
+
+    int it = 0;
+    for (;;) {
+        int any_prog = 0;
+        for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
+        int periodic_check = (it > 0 && true_res_period > 0 && it % true_res_period == 0);
+        if (!any_prog || periodic_check) {
+            /* True residual; restart converged components that fail it. */
+            rep->n_true_checks++;
+            orc_residual(op, bh, x, tmp, s);
+            for (int c = 0; c < 3; ++c) {
+                if (state[c] != ORC_CONVERGED) continue;
+                double trr = orc_dot(n, tmp[c], tmp[c]);
+                if (!(trr < tau2[c])) {
+                    memcpy(r[c], tmp[c], sizeof(double) * (size_t)n);
+                    memcpy(rh0[c], tmp[c], sizeof(double) * (size_t)n);
+                    rr[c] = trr;
+                    gamma[c] = orc_dot(n, rh0[c], r[c]);
+                    alphap[c] = 0.0;
+                    beta[c] = 0.0;
+                    gamma_prev[c] = 1.0;
+                    alpha[c] = 1.0;
+                    omega[c] = 1.0;
+                    memset(p[c], 0, sizeof(double) * (size_t)n);
+                    memset(Ap[c], 0, sizeof(double) * (size_t)n);
+                    state[c] = ORC_PROGRESSING;
+                    rep->n_replaced++;
+                }
+            }
+            any_prog = 0;
+            for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
+        }
+        if (!any_prog || it >= max_iter) break;
+        ++it;
+        int stall[3] = {0, 0, 0};
+
+        if (variant == ORC_ROBUST) {
+            /* p_i = r_{i-1} + beta_{i-1} p_{i-1} - alpha'_{i-1} A p_{i-1};
+             * a term with a zero coefficient is skipped (p, Ap unread). */
+            for (int c = 0; c < 3; ++c)
+                for (int64_t i = 0; i < n; ++i) {
+                    double v = r[c][i];
+                    if (beta[c] != 0.0) v += beta[c] * p[c][i];
+                    if (alphap[c] != 0.0) v -= alphap[c] * Ap[c][i];
+                    p[c][i] = v;
+                }
+        } else {
+            /* gamma_i = r0hat . r_{i-1}; beta_i = (gamma_i/gamma_{i-1})(alpha_{i-1}/omega_{i-1});
+             * p_i = r_{i-1} + beta_i (p_{i-1} - omega_{i-1} A p_{i-1}). */
+            for (int c = 0; c < 3; ++c) {
+                double g = orc_dot(n, rh0[c], r[c]);
+                double bt = 0.0;
+                if (gamma_prev[c] != 0.0 && omega[c] != 0.0) bt = (g / gamma_prev[c]) * (alpha[c] / omega[c]);
+                if (!orc_finite(bt)) bt = 0.0;
+                if (g == 0.0) stall[c] = 1;
+                gamma[c] = g;
+                beta[c] = bt;
+                for (int64_t i = 0; i < n; ++i) {
+                    double v = r[c][i];
+                    if (bt != 0.0) v += bt * (p[c][i] - omega[c] * Ap[c][i]);
+                    p[c][i] = v;
+                }
+            }
+        }
+        /* A p_i and delta_i = r0hat . A p_i; alpha_i = gamma_i / delta_i. */
+        orc_apply(op, (const double *const *)p, Ap);
+        for (int c = 0; c < 3; ++c) {
+            delta[c] = orc_dot(n, rh0[c], Ap[c]);
+            if (it == force_stall_iter && c == force_stall_comp) delta[c] = 0.0;
+            double a = 0.0;
+            if (delta[c] != 0.0 && orc_finite(delta[c])) a = gamma[c] / delta[c];
+            if (!orc_finite(a) || delta[c] == 0.0 || !orc_finite(delta[c])) {
+                a = 0.0;
+                stall[c] = 1;
+            }
+            alpha[c] = a;
+            /* r_star = r_{i-1} - alpha_i A p_i */
+            for (int64_t i = 0; i < n; ++i) s[c][i] = r[c][i] - a * Ap[c][i];
+        }
+        /* omega_i = (r_star . A r_star) / (A r_star . A r_star) */
+        orc_apply(op, (const double *const *)s, As);
+        for (int c = 0; c < 3; ++c) {
+            double tt = orc_dot(n, As[c], As[c]);
+            double ts = orc_dot(n, As[c], s[c]);
+            double w = 0.0;
+            if (tt != 0.0) w = ts / tt;
+            if (!orc_finite(w)) w = 0.0;
+            if (w == 0.0) stall[c] = 1;
+            if (variant == ORC_STANDARD) {
+                double ss = orc_dot(n, s[c], s[c]);
+                if (ss < tau2[c]) w = 0.0; /* x_star already meets the threshold */
+            }
+            omega[c] = w;
+            /* x_i = x_{i-1} + alpha_i p_i + omega_i r_star; r_i = r_star - omega_i A r_star */
+            for (int64_t i = 0; i < n; ++i) {
+                double xv = x[c][i] + alpha[c] * p[c][i];
+                x[c][i] = xv + w * s[c][i];
+                r[c][i] = s[c][i] - w * As[c][i];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            if (variant == ORC_ROBUST) {
+                /* gamma_{i+1} = r0hat . r_i; alpha'_i = gamma_{i+1}/delta_i; beta_i = alpha'_i/omega_i */
+                double g = orc_dot(n, rh0[c], r[c]);
+                double ap = 0.0, bt = 0.0;
+                if (!stall[c]) {
+                    ap = g / delta[c];
+                    if (!orc_finite(ap)) ap = 0.0;
+                    bt = ap / omega[c];
+                    if (!orc_finite(bt)) bt = 0.0;
+                }
+                if (g == 0.0) stall[c] = 1;
+                gamma[c] = g;
+                alphap[c] = ap;
+                beta[c] = bt;
+            } else {
+                gamma_prev[c] = gamma[c];
+            }
+            rr[c] = orc_dot(n, r[c], r[c]);
+            if (stall[c]) rep->stall_count[c]++;
+            state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : (stall[c] ? ORC_STALLED : ORC_PROGRESSING);
+            if (history && hl < history_cap) history[3 * hl + c] = rr[c];
+        }
+        ++hl;
+    }
+    /* final true residual for the report */
+    orc_residual(op, bh, x, tmp, s);
+    int any_prog = 0, any_stall = 0;
+    for (int c = 0; c < 3; ++c) {
+        rep->true_rr[c] = orc_dot(n, tmp[c], tmp[c]);
+        rep->rr[c] = rr[c];
+        rep->tau2[c] = tau2[c];
+        rep->state[c] = state[c];
+        any_prog |= state[c] == ORC_PROGRESSING;
+        any_stall |= state[c] == ORC_STALLED;
+    }
+    rep->iters = it;
+    rep->history_len = hl < history_cap ? hl : history_cap;
+    rep->status = any_prog ? ORC_NOT_CONVERGED : (any_stall ? ORC_STATUS_STALLED : ORC_OK);
+    free(buf);
+    return rep->status;
+}

@@ -1,0 +1,103 @@
+"""Pins of the oracle's kernel and neighbour search against facts fixed by the
+paper and by mathematics (not against the oracle itself)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle as O
+from paper_2206_14780_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_wendland_unit_integral():
+    # SPH kernels have unit integral (Section "Spatial discretization"):
+    # int W d^3r = 4 pi int_0^{2} q^2 w(q) dq = 1 for any h.
+    val, _ = integrate.quad(lambda q: 4.0 * math.pi * q * q * O.wendland_w(q), 0.0, 2.0,
+                            epsabs=1e-13, epsrel=1e-13, points=[1.0])
+    assert abs(val - 1.0) < 1e-12
+
+
+def test_wendland_f_is_radial_derivative_over_r():
+    # F(r, h) = (1/r) dW/dr  <=>  f(q) = w'(q)/q (Section "Spatial discretization").
+    q = np.linspace(0.05, 1.95, 39)
+    e = 1e-6
+    fd = (O.wendland_w(q + e) - O.wendland_w(q - e)) / (2 * e) / q
+    assert np.allclose(O.wendland_f(q), fd, rtol=1e-7, atol=1e-10)
+    assert np.all(O.wendland_f(q) < 0)  # W decreasing => F <= 0
+
+
+def test_wendland_compact_support_and_peak():
+    assert O.wendland_w(2.0) == 0.0 and O.wendland_f(2.0) == 0.0
+    assert O.wendland_w(2.5) == 0.0 and O.wendland_f(3.0) == 0.0
+    assert abs(O.wendland_w(0.0) - 21.0 / (16.0 * math.pi)) < 1e-15
+
+
+def _lattice_count(radius):
+    v = np.arange(-8, 9)
+    I, J, K = np.meshgrid(v, v, v, indexing="ij")
+    r2 = (I ** 2 + J ** 2 + K ** 2).ravel()
+    return int(((r2 > 0) & (r2 < radius * radius)).sum())
+
+
+@pytest.mark.parametrize("hf,key", [(1.3, "wendland"), (2.5, "wendland25")])
+def test_lattice_neighbour_count(hf, key):
+    # Every interior particle of an unjittered cubic lattice has exactly the
+    # number of integer vectors v != 0 with |v| < 2 hf (the paper prints
+    # "around 80" for hf = 1.3 and "about twice" the Gaussian's 250 for 2.5).
+    gold = json.load(open(os.path.join(GOLD, "kernel_neighbours.json")))
+    expect = _lattice_count(2 * hf)
+    if key == "wendland":
+        assert expect == 80 == gold["wendland_neighbours_printed_approx"]
+    else:
+        assert abs(expect / gold["gaussian_neighbours_printed_approx"] - 2.0) < 0.1
+    n = 12 if hf < 2 else 14
+    pos, pt = W.lattice((n, n, n), 1.0)
+    rp, cols = O.neighbors(pos, [n, n, n], hf, lo=[0, 0, 0], method="grid")
+    assert np.all(np.diff(rp) == expect)
+
+
+def _random_system(seed, n=(7, 6, 9), periodic=(1, 1, 0), jitter=0.3, hf=1.3, dp=1.0):
+    rng = np.random.default_rng(seed)
+    walls = tuple((not p, not p) for p in periodic)
+    pos, pt = W.lattice(n, dp, walls=walls, jitter=jitter, rng=rng)
+    perm = rng.permutation(pos.shape[0])
+    pos, pt = pos[perm], pt[perm]
+    lo = np.array([0.0 if p else -3 * dp for p in periodic])
+    period = np.array([n[a] * dp if periodic[a] else 0.0 for a in range(3)])
+    return pos, pt, lo, period, hf * dp
+
+
+@pytest.mark.parametrize("seed,periodic,hf", [(1, (1, 1, 0), 1.3), (2, (0, 0, 0), 1.3),
+                                              (3, (1, 1, 1), 1.0), (4, (1, 0, 1), 1.7)])
+def test_brute_force_equals_cell_grid(seed, periodic, hf):
+    pos, pt, lo, period, h = _random_system(seed, periodic=periodic, hf=hf)
+    a = O.neighbors(pos, period, h, method="brute")
+    b = O.neighbors(pos, period, h, lo=lo, method="grid")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_neighbour_relation_is_symmetric_and_irreflexive():
+    pos, pt, lo, period, h = _random_system(5, periodic=(1, 1, 0))
+    rp, cols = O.neighbors(pos, period, h, method="brute")
+    n = pos.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert not np.any(rows == cols)
+    pairs = set(zip(rows.tolist(), cols.tolist()))
+    assert all((j, i) in pairs for (i, j) in pairs)
+    # ascending columns inside each row
+    for i in range(0, n, 17):
+        seg = cols[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+
+
+def test_neighbours_minimum_image_by_hand():
+    # Two particles across a periodic face are neighbours through the image.
+    pos = np.array([[0.1, 0.5, 0.5], [9.9, 0.5, 0.5], [5.0, 0.5, 0.5]])
+    for method in ("brute", "grid"):
+        rp, cols = O.neighbors(pos, [10.0, 0.0, 0.0], 0.5, lo=[0, 0, 0], method=method)
+        assert rp.tolist() == [0, 1, 2, 2] and cols.tolist() == [1, 0]
