@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the semi-implicit SPH viscous solve on one MI355X.
+
+Workload: the 100^3 jittered open-top tank (1,157,308 particles with three
+wall layers, dummy walls, nu = 10, dt nu/dp^2 = 50, u0 ~ N(0, 0.1^2), previous
+step start), FP32 vectors and operator with FP64 scalars, robust BiCGSTAB to a
+1e-6 relative residual.  One step = the whole hot path on inputs already in
+HBM: neighbour build by counting sort, cached operator build, and the solve.
+
+Prints one JSON line: particle-iterations per second of the whole step, the
+roofline of the dominant kernel (the operator launch that computes A r_star
+with its dot products, timed with HIP events on the library's stream over the
+timed region), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-6 residual per solve, particle-iters/s, HBM GB/s; plain vs learned"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100, help="fluid particles per side of the tank")
+    ap.add_argument("--op-mode", choices=["cached", "onthefly"], default="cached")
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--cpu-sample-iters", type=int, default=4,
+                    help="BiCGSTAB iterations of the oracle's timed sample (0 = skip)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, sample_iters):
+    """The FP64 oracle (as it stands) on the same tank: neighbour grid, then
+    `sample_iters` robust BiCGSTAB iterations from the same start."""
+    import oracle as O
+    t0 = time.perf_counter()
+    nbr = O.neighbors(w.pos, w.period, w.h, lo=w.lo, method="grid")
+    t_nbr = time.perf_counter() - t0
+    op = O.Operator.from_workload(w, nbr=nbr)
+    t0 = time.perf_counter()
+    _, rep, _ = O.solve(op, w.rhs, X0=w.x0, tol=w.tol, max_iter=sample_iters, true_res_period=0)
+    t_solve = time.perf_counter() - t0
+    iters = max(rep["iters"], 1)
+    return {
+        "value": w.n * iters / t_solve,
+        "unit": "particle-iters/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"full {w.n}-particle tank, FP64 robust BiCGSTAB, first {iters} iterations "
+                   f"({t_solve:.1f} s; neighbour grid {t_nbr:.1f} s not counted)"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver has no "
+              "multi-GPU domain decomposition.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = S.SPH_F32 if args.prec == "f32" else S.SPH_F64
+    op_mode = S.SPH_OP_CACHED if args.op_mode == "cached" else S.SPH_OP_ONTHEFLY
+    w = W.open_box(n=args.n)
+    ctx = S.Context(0)
+    parts = S.device_particles(w)
+    dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
+    rhs = S.device_vec3(w.rhs, prec)
+    x0 = S.device_vec3(w.x0, prec)
+    x = [t.clone() for t in x0]
+    params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=op_mode)
+    opts = S.make_opts(tol=w.tol, x0_given=True, profile=True)
+    build_ms = []
+
+    def step():
+        for a, b in zip(x, x0):
+            a.copy_(b)
+        t0 = time.perf_counter()
+        nb = ctx.sph_build_neighbors(parts, dom)
+        build_ms.append((time.perf_counter() - t0) * 1e3)
+        rep = ctx.sph_visc_solve(nb, None, parts, params, prec, rhs, x, opts)
+        nb.free()
+        assert rep["status"] == S.SPH_OK, rep
+        return rep
+
+    print(f"[bench] workload open_box{args.n} n={w.n} prec={args.prec} op={args.op_mode}", flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    build_ms.clear()
+    t0 = time.perf_counter()
+    reps = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    ms_per_step = total_s * 1e3 / args.steps
+    iters = reps[-1]["iters"]
+    assert all(r["iters"] == iters for r in reps)
+    value = w.n * iters * args.steps / total_s
+    solve_ms = [r["setup_ms"] + r["iterate_ms"] for r in reps]
+    print(f"[bench] {args.steps} steps, {ms_per_step:.2f} ms/step, {iters} iterations", flush=True)
+
+    # dominant kernel: the A r_star operator launch (one per iteration)
+    a_ms = sum(r["apply_ms"] for r in reps) / max(sum(r["apply_launches"] for r in reps), 1)
+    esz = 4 if prec == S.SPH_F32 else 8
+    nnz, slots = reps[-1]["mat_nnz"], reps[-1]["mat_slots"]
+    nslices = (w.n + 63) // 64
+    # algorithmic bytes per launch: every stored nonzero (column index +
+    # coefficient), x (3 values) and y (3 values) and the diagonal per row,
+    # one slice pointer per 64 rows
+    alg_bytes = nnz * (4 + esz) + w.n * (7 * esz) + nslices * 8
+    roofline = None
+    if op_mode == S.SPH_OP_CACHED and a_ms > 0:
+        achieved = alg_bytes / (a_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"k_apply_sell<{'float' if esz == 4 else 'double'}, kDotA2>",
+                    "avg_launch_ms": round(a_ms, 4), "alg_bytes_per_launch": int(alg_bytes),
+                    "mat_nnz": int(nnz), "mat_slots": int(slots)}
+
+    cpu = None
+    if args.cpu_sample_iters > 0:
+        print("[bench] cpu baseline (oracle)", flush=True)
+        cpu = cpu_baseline(w, args.cpu_sample_iters)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"open-top tank {args.n}^3 jittered fluid + 3 wall layers (dummy), "
+                               f"nu=10, dt*nu/dp^2=50, robust BiCGSTAB to 1e-6, "
+                               f"{args.prec} vectors/operator + f64 scalars, {args.op_mode} operator",
+                   "n_particles": w.n, "tol": w.tol, "scalar_dtype": "f64"},
+        "iterations": iters,
+        "time_to_tol_ms": float(np.median(solve_ms)),
+        "neighbour_build_ms": float(np.median(build_ms)),
+        "true_rel_res": [float(np.sqrt(t / b)) if b > 0 else 0.0
+                         for t, b in zip(reps[-1]["true_rr"], reps[-1]["bb"])],
+        "launches_per_solve": reps[-1]["launches"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

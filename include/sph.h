@@ -1,0 +1,207 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) semi-implicit SPH viscous solver.
+ *
+ * The library solves the implicit viscous system of Bilotta et al., "A
+ * numerically robust, parallel-friendly variant of BiCGSTAB for the
+ * semi-implicit integration of the viscous term in Smoothed Particle
+ * Hydrodynamics" (arXiv 2206.14780), Section "Shared formulation":
+ *
+ *     A(dt) V = B,   A: N x N (one row per particle),  V, B: N x 3,
+ *
+ * three systems (one per velocity component) sharing one matrix, solved by
+ * the paper's restructured ("robust") BiCGSTAB (Section "Restructuring the
+ * stabilized biconjugate gradient method") or by the textbook BiCGSTAB.
+ *
+ * Conventions for every call:
+ *   - Pointers inside sph_particles and the x/y/rhs arrays are DEVICE pointers
+ *     owned by the caller, in the caller's (original) particle order, unless
+ *     the comment says "host".  The library never frees them.
+ *   - Work is issued on the context's HIP stream.  sph_visc_apply is
+ *     asynchronous; sph_build_neighbors, sph_neighbors_export and
+ *     sph_visc_solve return after the stream work they issued has finished.
+ *   - Negative status = failure, outputs undefined.  Positive status = the
+ *     outputs are valid and the report says why the solve stopped.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Matrix rows, taking the diffusive sign of eq. kab (the printed sign would
+ *     make the fluid rows lose diagonal dominance): with pair weight w_ba = -2 mubar_ab m_a F(r_ab)/(rho_a rho_b)
+ *       fluid row b:        A_bb = 1 + dt sum_a w_ba,  A_ba = -dt w_ba     (eqs. diag, offdiag)
+ *       dynamic wall row b: identity                          (eq. implicit-system-dyn-full)
+ *       dummy wall row b:   A_bb = 1, A_ba = W_ba / sum_{a' fluid} W_ba' for fluid a,
+ *                           identity if b has no fluid neighbour
+ *                                                             (eq. implicit-system-dummy-full)
+ *     W, F: Wendland psi_{3,1} kernel of radius 2h (Section "Smoothing kernel choice").
+ *     Neighbours: a != b with |r_a - r_b|^2 < (2h)^2, minimum image on periodic axes.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx; /* device, stream binding, workspace */
+typedef struct sph_nbr sph_nbr; /* cell-linked lists of one particle configuration */
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_STALLED = 1,        /* no component progressing, at least one stalled */
+    SPH_NOT_CONVERGED = 2,  /* max_iter reached with a component still progressing */
+    SPH_E_ARG = -1,         /* invalid argument (null pointer, size, enum, geometry) */
+    SPH_E_OOM = -2,         /* device allocation failed */
+    SPH_E_HIP = -3,         /* HIP runtime error (message via sph_last_error) */
+    SPH_E_OVERFLOW = -4,    /* output capacity too small (sph_neighbors_export) */
+    SPH_E_NONFINITE = -5    /* non-finite right-hand side */
+} sph_status;
+
+enum { SPH_F64 = 0, SPH_F32 = 1 };                 /* vector / operator precision */
+enum { SPH_FLUID = 0, SPH_WALL = 1 };              /* particle type */
+enum { SPH_WALL_DYNAMIC = 0, SPH_WALL_DUMMY = 1 }; /* boundary model (Section "Boundary conditions") */
+enum { SPH_AVG_ARITH = 0, SPH_AVG_HARMONIC = 1 };  /* pairwise viscosity mean (Section "Discretized equations") */
+enum { SPH_ROBUST = 0, SPH_STANDARD = 1 };         /* BiCGSTAB variant */
+enum { SPH_OP_CACHED = 0, SPH_OP_ONTHEFLY = 1 };   /* operator evaluation (see sph_visc_params) */
+enum { SPH_CONVERGED = 0, SPH_STATE_STALLED = 1, SPH_PROGRESSING = 2 }; /* per-component state */
+
+/* One particle configuration.  n >= 1; all arrays have n entries. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;       /* positions */
+    const double *mass, *rho, *mu; /* mass, density, DYNAMIC viscosity (mu = nu rho) */
+    const uint8_t *type;           /* SPH_FLUID or SPH_WALL */
+} sph_particles;
+
+/* Domain box.  On a periodic axis the period is hi - lo (> 0) and
+ * distances use the minimum image, so each pair counts once; on other axes
+ * particles outside [lo, hi] are binned into the edge cells (still exact,
+ * only slower). */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t periodic[3];
+    double h; /* smoothing length; support radius 2h */
+} sph_domain;
+
+/* Parameters of A(dt).
+ *   jacobi: 1 = left Jacobi scaling, the operator and solver use D^-1 A and
+ *           D^-1 B with D = diag(A) (appendix "Implementation notes").
+ *   op_mode: SPH_OP_CACHED evaluates every pair coefficient once per call in
+ *           FP64 and keeps the matrix in HBM (sliced ELLPACK, rounded to the
+ *           vector precision) for all applications of that call;
+ *           SPH_OP_ONTHEFLY re-evaluates the coefficients from positions in
+ *           every application (the paper's matrix-free gemv). */
+typedef struct {
+    double dt;
+    int32_t wall;    /* SPH_WALL_DYNAMIC / SPH_WALL_DUMMY */
+    int32_t avg;     /* SPH_AVG_ARITH / SPH_AVG_HARMONIC */
+    int32_t jacobi;  /* 0 / 1 */
+    int32_t op_mode; /* SPH_OP_CACHED / SPH_OP_ONTHEFLY */
+} sph_visc_params;
+
+/* Solver options.
+ *   tol:   relative tolerance eps; component c converges when r.r < tau2_c,
+ *          tau2_c = max(eps^2 b.b, floor) on the (scaled) system
+ *          (Section "Restructuring the Conjugate Gradient", stopping criterion).
+ *   floor: lower bound of tau2; < 0 selects FLT_MIN (SPH_F32) or DBL_MIN (SPH_F64).
+ *   true_res_period: every that many iterations, and whenever no component
+ *          is progressing, the residual b - A x is recomputed in FP64 with the
+ *          on-the-fly operator; a converged component that fails it is
+ *          restarted from that residual.  0 = only when no component progresses.
+ *   x0_given: 1 = x holds the initial guess on entry, 0 = start from zero.
+ *   poll_every: iterations issued between two host reads of the device stop
+ *          flag (0 = library default).  Does not change the result.
+ *   force_stall_iter / force_stall_comp: test hook; at that iteration that
+ *          component's delta is treated as zero.  -1 = off.
+ *   profile: 1 = bracket every executed launch of the second operator kernel
+ *          of an iteration (A r_star and its dot products) with HIP events on
+ *          the context stream and report their total time (apply_ms). */
+typedef struct {
+    double tol;
+    int32_t max_iter;
+    int32_t variant; /* SPH_ROBUST / SPH_STANDARD */
+    double floor;
+    int32_t true_res_period;
+    int32_t x0_given;
+    int32_t poll_every;
+    int32_t force_stall_iter;
+    int32_t force_stall_comp;
+    int32_t profile;
+} sph_solve_opts;
+
+/* Solve report (host memory).  history, if non-null, is a host buffer of
+ * history_cap x 3 doubles that receives r.r per component at the end of
+ * each iteration (row 0 = initial residual). */
+typedef struct {
+    int32_t iters;
+    int32_t status;
+    int32_t state[3];       /* SPH_CONVERGED / SPH_STATE_STALLED / SPH_PROGRESSING */
+    int32_t stall_count[3]; /* iterations in which the component broke down */
+    double rr[3];           /* final recursive r.r of the scaled system */
+    double bb[3];           /* b.b of the scaled right-hand side */
+    double tau2[3];
+    double true_rr[3];      /* final FP64 (b - A x).(b - A x) of the scaled system */
+    int32_t n_true_checks;
+    int32_t n_replaced;
+    double *history;        /* host, may be null */
+    int32_t history_cap;
+    int32_t history_len;
+    double setup_ms;        /* device time: gathers, matrix build, initial residual */
+    double iterate_ms;      /* device time of the iterations and residual checks */
+    int32_t launches;       /* kernel launches issued by the solve */
+    int64_t mat_nnz;        /* off-diagonal entries of the cached matrix (SPH_OP_CACHED) */
+    int64_t mat_slots;      /* stored entries including slice padding (SPH_OP_CACHED) */
+    double apply_ms;        /* with opts->profile: summed duration of the timed launches */
+    int32_t apply_launches; /* with opts->profile: number of timed launches */
+} sph_solve_report;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; null = the device's null stream).  *ctx receives the handle. */
+sph_status sph_create(sph_ctx **ctx, int32_t device, void *hip_stream);
+/* Release the context and all its device workspace. */
+sph_status sph_destroy(sph_ctx *ctx);
+/* Re-bind the context to another stream of the same device. */
+sph_status sph_set_stream(sph_ctx *ctx, void *hip_stream);
+/* Message of the last failure on this context (static storage of the context). */
+const char *sph_last_error(const sph_ctx *ctx);
+const char *sph_status_str(sph_status s);
+
+/* Cell-linked lists by counting sort (Section "Smoothing kernel choice" for
+ * the support radius; appendix on relative positions for the cell grid):
+ * cells of side >= 2h, particles ordered by cell and, inside a cell, by
+ * original index.  Positions are copied; the handle stays valid after the
+ * caller's arrays change.  *out receives a new handle (free it with
+ * sph_neighbors_free).  Only the positions of `p` are read. */
+sph_status sph_build_neighbors(sph_ctx *ctx, const sph_particles *p, const sph_domain *dom,
+                               sph_nbr **out);
+/* Number of particles and of (directed) neighbour pairs of the handle. */
+sph_status sph_neighbors_info(sph_ctx *ctx, const sph_nbr *nb, int64_t *n, int64_t *nnz);
+/* Neighbour lists in canonical form: CSR over original particle indices,
+ * columns ascending.  row_ptr: device, n + 1 entries; cols: device, cap
+ * entries.  *nnz (host) receives the pair count; SPH_E_OVERFLOW if cap < nnz. */
+sph_status sph_neighbors_export(sph_ctx *ctx, const sph_nbr *nb, int64_t *row_ptr,
+                                int32_t *cols, int64_t cap, int64_t *nnz);
+sph_status sph_neighbors_free(sph_nbr *nb);
+
+/* y = A x (or D^-1 A x when params->jacobi) for the three components.
+ * x[c], y[c]: device arrays of n doubles (prec SPH_F64) or floats (SPH_F32).
+ * x and y must not overlap.  Coefficients are evaluated in FP64 in both
+ * precisions; SPH_OP_CACHED rounds them to the vector precision. */
+sph_status sph_visc_apply(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
+                          const sph_visc_params *params, int32_t prec, const void *const x[3],
+                          void *const y[3]);
+
+/* Solve A V = B.  nb may be null, then dom must be given and the lists are
+ * built inside the call.  rhs[c]: device, n values of the precision;
+ * x[c]: device, n values; initial guess on entry if opts->x0_given, solution
+ * on exit.  Vector updates and operator run in `prec`; every inner product
+ * and every scalar of the recurrences is FP64 in both precisions.  With the
+ * dummy model the wall rows of V are the viscous velocities. */
+sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom,
+                          const sph_particles *p, const sph_visc_params *params, int32_t prec,
+                          const void *const rhs[3], void *const x[3], const sph_solve_opts *opts,
+                          sph_solve_report *report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -39,7 +39,8 @@
  *   - true residual: every `true_res_period` iterations and whenever no
  *     component is progressing, r_true = b - A x is recomputed; a component
  *     marked converged whose true residual fails the threshold is restarted
- *     from r_true (r0hat = r_true, alpha' = beta = 0) and made progressing.
+ *     from r_true (r0hat = r_true, alpha' = beta = 0) and made progressing;
+ *     after three such restarts it is reported stalled instead.
  *   - textbook variant: when the half-step residual s already meets the
  *     threshold the component takes omega = 0 (x = x + alpha p, r = s).
  */
@@ -480,6 +481,7 @@ typedef struct {
 
 #define ORC_ROBUST 0
 #define ORC_STANDARD 1
+#define ORC_MAX_RESTARTS 3
 
 static double orc_dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
@@ -536,7 +538,7 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
         for (int64_t i = 0; i < n; ++i) bh[c][i] = op->jacobi ? b[c][i] / D[0][i] : b[c][i];
 
     double gamma[3], gamma_prev[3], alpha[3], alphap[3], beta[3], omega[3], delta[3], tau2[3], rr[3];
-    int state[3];
+    int state[3], restarts[3] = {0, 0, 0};
     for (int c = 0; c < 3; ++c) {
         rep->bb[c] = orc_dot(n, bh[c], bh[c]);
         if (!orc_finite(rep->bb[c])) {
@@ -578,7 +580,10 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
             for (int c = 0; c < 3; ++c) {
                 if (state[c] != ORC_CONVERGED) continue;
                 double trr = orc_dot(n, tmp[c], tmp[c]);
-                if (!(trr < tau2[c])) {
+                if (!(trr < tau2[c]) && restarts[c] >= ORC_MAX_RESTARTS) {
+                    state[c] = ORC_STALLED; /* precision cannot reach the tolerance */
+                } else if (!(trr < tau2[c])) {
+                    restarts[c]++;
                     memcpy(r[c], tmp[c], sizeof(double) * (size_t)n);
                     memcpy(rh0[c], tmp[c], sizeof(double) * (size_t)n);
                     rr[c] = trr;

@@ -1,0 +1,347 @@
+// The viscous operator A(dt): particle data gathers, the cached sliced-ELL
+// matrix (coefficients evaluated once per call in FP64), and the operator
+// kernels used by sph_visc_apply and the solver.
+#include "operator_kernels.hpp"
+
+namespace sph {
+
+// ---------------------------------------------------------------------------
+// Gathers between the caller's order and cell order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gather_props(int64_t n, const int32_t* __restrict__ perm,
+                                                         const double* __restrict__ m,
+                                                         const double* __restrict__ r,
+                                                         const double* __restrict__ mu,
+                                                         const uint8_t* __restrict__ t,
+                                                         double* __restrict__ om, double* __restrict__ orr,
+                                                         double* __restrict__ omu,
+                                                         uint8_t* __restrict__ ot) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t o = perm[s];
+    om[s] = m[o];
+    orr[s] = r[o];
+    omu[s] = mu[o];
+    ot[s] = t[o];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_vec3(int64_t n, const int32_t* __restrict__ perm,
+                                                        const T* __restrict__ a, const T* __restrict__ b,
+                                                        const T* __restrict__ c, T* __restrict__ dst) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t o = perm[s];
+    V3<T> v;
+    v.x = a[o];
+    v.y = b[o];
+    v.z = c[o];
+    st3(dst, s, v);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_vec3(int64_t n, const int32_t* __restrict__ perm,
+                                                         const T* __restrict__ src, T* __restrict__ a,
+                                                         T* __restrict__ b, T* __restrict__ c) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t o = perm[s];
+    V3<T> v = ld3(src, s);
+    a[o] = v.x;
+    b[o] = v.y;
+    c[o] = v.z;
+}
+
+sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out) {
+    const int64_t n = nb->n;
+    double *m = nullptr, *r = nullptr, *mu = nullptr;
+    uint8_t* t = nullptr;
+    SPH_TRY(ctx->ensure_t(kMass, n, &m));
+    SPH_TRY(ctx->ensure_t(kRho, n, &r));
+    SPH_TRY(ctx->ensure_t(kMu, n, &mu));
+    SPH_TRY(ctx->ensure_t(kType, n, &t));
+    hipLaunchKernelGGL(k_gather_props, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
+                       nb->perm, p->mass, p->rho, p->mu, p->type, m, r, mu, t);
+    SPH_LAUNCHED("k_gather_props");
+    out->mass = m;
+    out->rho = r;
+    out->mu = mu;
+    out->type = t;
+    return SPH_OK;
+}
+
+template <typename T>
+sph_status gather_vec3(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst) {
+    hipLaunchKernelGGL(k_gather_vec3<T>, dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       nb->n, nb->perm, (const T*)src[0], (const T*)src[1], (const T*)src[2], dst);
+    SPH_LAUNCHED("k_gather_vec3");
+    return SPH_OK;
+}
+
+template <typename T>
+sph_status scatter_vec3(sph_ctx* ctx, const sph_nbr* nb, const T* src, void* const dst[3]) {
+    hipLaunchKernelGGL(k_scatter_vec3<T>, dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0,
+                       ctx->stream, nb->n, nb->perm, src, (T*)dst[0], (T*)dst[1], (T*)dst[2]);
+    SPH_LAUNCHED("k_scatter_vec3");
+    return SPH_OK;
+}
+
+template sph_status gather_vec3<float>(sph_ctx*, const sph_nbr*, const void* const[3], float*);
+template sph_status gather_vec3<double>(sph_ctx*, const sph_nbr*, const void* const[3], double*);
+template sph_status scatter_vec3<float>(sph_ctx*, const sph_nbr*, const float*, void* const[3]);
+template sph_status scatter_vec3<double>(sph_ctx*, const sph_nbr*, const double*, void* const[3]);
+
+// ---------------------------------------------------------------------------
+// Matrix build, pass 1: entries per row, FP64 diagonal, dummy-wall kernel sum.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_row_count(NbrView nv, PartView pv, OpParams op,
+                                                      int32_t* __restrict__ cnt,
+                                                      double* __restrict__ diag64,
+                                                      double* __restrict__ wsum) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nv.n) return;
+    const int32_t row = (int32_t)b;
+    int32_t c = 0;
+    double d = 1.0, sW = 0.0;
+    if (pv.type[row] == SPH_FLUID) {
+        double sw = 0.0;
+        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+            sw += pair_w(pv, nv.g, op.avg, row, a, r2);
+            ++c;
+        });
+        d = 1.0 + op.dt * sw;
+    } else if (op.wall == SPH_WALL_DUMMY) {
+        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+            if (pv.type[a] != SPH_FLUID) return;
+            sW += pair_W(nv.g, r2);
+            ++c;
+        });
+        if (!(sW > 0.0)) c = 0;
+    }
+    if (cnt) cnt[row] = c;
+    diag64[row] = d;
+    if (wsum) wsum[row] = sW;
+}
+
+// Slice size = 64 x (longest row of the slice).
+__global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslices,
+                                                       const int32_t* __restrict__ cnt,
+                                                       int64_t* __restrict__ size,
+                                                       unsigned long long* __restrict__ nnz) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    int32_t w = 0;
+    int64_t tot = 0;
+    for (int l = 0; l < kWave; ++l) {
+        int64_t r = s * kWave + l;
+        if (r < n) {
+            w = max(w, cnt[r]);
+            tot += cnt[r];
+        }
+    }
+    size[s] = (int64_t)w * kWave;
+    atomicAdd(nnz, (unsigned long long)tot);
+}
+
+// Pass 2: write columns and coefficients.  Coefficients are evaluated in
+// FP64 and rounded once to T.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, OpParams op,
+                                                     const double* __restrict__ diag64,
+                                                     const double* __restrict__ wsum,
+                                                     const int64_t* __restrict__ sl_ptr,
+                                                     int32_t* __restrict__ cols, T* __restrict__ coef,
+                                                     T* __restrict__ dg, int64_t nslices) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nslices * kWave) return;
+    const int64_t s = r / kWave;
+    const int lane = (int)(r % kWave);
+    const int64_t base = sl_ptr[s] + lane;
+    const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
+    int32_t k = 0;
+    int32_t pad_col = 0;
+    if (r < nv.n) {
+        const int32_t row = (int32_t)r;
+        pad_col = row;
+        const double D = diag64[row];
+        if (pv.type[row] == SPH_FLUID) {
+            for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+                double aba = -op.dt * pair_w(pv, nv.g, op.avg, row, a, r2);
+                double c = op.jacobi ? aba / D : aba;
+                cols[base + (int64_t)k * kWave] = a;
+                coef[base + (int64_t)k * kWave] = (T)c;
+                ++k;
+            });
+            dg[row] = op.jacobi ? T(1) : (T)D;
+        } else {
+            const double sW = wsum[row];
+            if (op.wall == SPH_WALL_DUMMY && sW > 0.0) {
+                for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+                    if (pv.type[a] != SPH_FLUID) return;
+                    cols[base + (int64_t)k * kWave] = a;
+                    coef[base + (int64_t)k * kWave] = (T)(pair_W(nv.g, r2) / sW);
+                    ++k;
+                });
+            }
+            dg[row] = T(1);
+        }
+    }
+    for (; k < width; ++k) {
+        cols[base + (int64_t)k * kWave] = pad_col;
+        coef[base + (int64_t)k * kWave] = T(0);
+    }
+}
+
+sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
+                      const double** diag64) {
+    double* d = nullptr;
+    SPH_TRY(ctx->ensure_t(kDiag64, nb->n, &d));
+    hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       nb->view(), pv, op, (int32_t*)nullptr, d, (double*)nullptr);
+    SPH_LAUNCHED("k_row_count");
+    *diag64 = d;
+    return SPH_OK;
+}
+
+template <typename T>
+sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op, Sell<T>* out,
+                      const double** diag64, int64_t* nnz_out, int64_t* slots_out) {
+    const int64_t n = nb->n;
+    const int64_t nslices = ceil_div(n, kWave);
+    int32_t* cnt = nullptr;
+    double *d = nullptr, *ws = nullptr;
+    int64_t *size = nullptr, *ptr = nullptr;
+    SPH_TRY(ctx->ensure_t(kCnt, n, &cnt));
+    SPH_TRY(ctx->ensure_t(kDiag64, n, &d));
+    SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
+    SPH_TRY(ctx->ensure_t(kSlSize, nslices, &size));
+    SPH_TRY(ctx->ensure_t(kSlPtr, nslices + 1, &ptr));
+    hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       nb->view(), pv, op, cnt, d, ws);
+    unsigned long long* nnz_dev = nullptr;
+    SPH_TRY(ctx->ensure_t(kNnzCount, 1, &nnz_dev));
+    SPH_HIP(hipMemsetAsync(nnz_dev, 0, sizeof(unsigned long long), ctx->stream));
+    hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       n, nslices, cnt, size, nnz_dev);
+    SPH_LAUNCHED("k_row_count/k_slice_size");
+    SPH_TRY(scan_i64(ctx, size, ptr, nslices));
+    int64_t nnzp = 0;
+    unsigned long long nnz_true = 0;
+    SPH_HIP(hipMemcpyAsync(&nnzp, ptr + nslices, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    SPH_HIP(hipMemcpyAsync(&nnz_true, nnz_dev, sizeof(nnz_true), hipMemcpyDeviceToHost, ctx->stream));
+    SPH_HIP(hipStreamSynchronize(ctx->stream));
+    if (nnz_out) *nnz_out = (int64_t)nnz_true;
+    if (slots_out) *slots_out = nnzp;
+    int32_t* cols = nullptr;
+    T* coef = nullptr;
+    T* dg = nullptr;
+    SPH_TRY(ctx->ensure_t(kCols, (size_t)(nnzp > 0 ? nnzp : 1), &cols));
+    SPH_TRY(ctx->ensure_t(kCoef, (size_t)(nnzp > 0 ? nnzp : 1), &coef));
+    SPH_TRY(ctx->ensure_t(kDg, n, &dg));
+    hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
+                       ctx->stream, nb->view(), pv, op, d, ws, ptr, cols, coef, dg, nslices);
+    SPH_LAUNCHED("k_row_fill");
+    out->nslices = nslices;
+    out->sl_ptr = ptr;
+    out->cols = cols;
+    out->coef = coef;
+    out->dg = dg;
+    if (diag64) *diag64 = d;
+    return SPH_OK;
+}
+
+template sph_status build_sell<float>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&, Sell<float>*,
+                                      const double**, int64_t*, int64_t*);
+template sph_status build_sell<double>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&,
+                                       Sell<double>*, const double**, int64_t*, int64_t*);
+
+Launch make_launch(int64_t n) {
+    Launch L;
+    L.n = n;
+    const int64_t nslices = ceil_div(n, kWave);
+    // operator kernels: one wavefront per slice at a time, 4 waves per block
+    int64_t ga = ceil_div(nslices, 4 * 2);
+    if (ga > 2048) ga = 2048;
+    if (ga >= 64) ga = (ga / kNumXcd) * kNumXcd;
+    if (ga < 1) ga = 1;
+    int64_t gs = ceil_div(n, (int64_t)kBlock * 4);
+    if (gs > 1024) gs = 1024;
+    if (gs >= 64) gs = (gs / kNumXcd) * kNumXcd;
+    if (gs < 1) gs = 1;
+    L.grid_apply = (int32_t)ga;
+    L.grid_stream = (int32_t)gs;
+    return L;
+}
+
+template <typename T>
+sph_status apply_plain(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op, int mode,
+                       const Sell<T>* sell, const T* x, T* y) {
+    const Launch L = make_launch(nb->n);
+    if (mode == SPH_OP_CACHED) {
+        hipLaunchKernelGGL((k_apply_sell<T, kDotNone>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
+                           (const int32_t*)nullptr, nb->n, *sell, x, y, (const T*)nullptr, (double*)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_apply_otf<T, kDotNone>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
+                           (const int32_t*)nullptr, nb->view(), pv, op, x, y, (const T*)nullptr,
+                           (const double*)nullptr, (double*)nullptr);
+    }
+    SPH_LAUNCHED("apply");
+    return SPH_OK;
+}
+
+template sph_status apply_plain<float>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&, int,
+                                       const Sell<float>*, const float*, float*);
+template sph_status apply_plain<double>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&, int,
+                                        const Sell<double>*, const double*, double*);
+
+}  // namespace sph
+
+using namespace sph;
+
+sph_status check_particles(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p) {
+    if (!p) return ctx->fail(SPH_E_ARG, "null particles");
+    if (p->n != nb->n) return ctx->fail(SPH_E_ARG, "particle count differs from the neighbour handle");
+    if (!p->mass || !p->rho || !p->mu || !p->type) return ctx->fail(SPH_E_ARG, "null particle array");
+    return SPH_OK;
+}
+
+sph_status check_params(sph_ctx* ctx, const sph_visc_params* v, int32_t prec) {
+    if (!v) return ctx->fail(SPH_E_ARG, "null params");
+    if (!(v->dt >= 0.0) || !std::isfinite(v->dt)) return ctx->fail(SPH_E_ARG, "params: dt must be finite and >= 0");
+    if (v->wall != SPH_WALL_DYNAMIC && v->wall != SPH_WALL_DUMMY) return ctx->fail(SPH_E_ARG, "params: wall");
+    if (v->avg != SPH_AVG_ARITH && v->avg != SPH_AVG_HARMONIC) return ctx->fail(SPH_E_ARG, "params: avg");
+    if (v->op_mode != SPH_OP_CACHED && v->op_mode != SPH_OP_ONTHEFLY) return ctx->fail(SPH_E_ARG, "params: op_mode");
+    if (prec != SPH_F32 && prec != SPH_F64) return ctx->fail(SPH_E_ARG, "prec");
+    return SPH_OK;
+}
+
+template <typename T>
+static sph_status apply_entry(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p,
+                              const sph_visc_params* v, const void* const x[3], void* const y[3]) {
+    PartView pv;
+    SPH_TRY(gather_props(ctx, nb, p, &pv));
+    OpParams op{v->dt, v->wall, v->avg, v->jacobi ? 1 : 0};
+    T *xin = nullptr, *yout = nullptr;
+    SPH_TRY(ctx->ensure_t(kApplyIn, (size_t)nb->n * 3, &xin));
+    SPH_TRY(ctx->ensure_t(kApplyOut, (size_t)nb->n * 3, &yout));
+    SPH_TRY(gather_vec3<T>(ctx, nb, x, xin));
+    Sell<T> sell{};
+    if (v->op_mode == SPH_OP_CACHED) SPH_TRY(build_sell<T>(ctx, nb, pv, op, &sell, nullptr));
+    SPH_TRY(apply_plain<T>(ctx, nb, pv, op, v->op_mode, &sell, xin, yout));
+    SPH_TRY(scatter_vec3<T>(ctx, nb, yout, y));
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_visc_apply(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p,
+                                     const sph_visc_params* params, int32_t prec, const void* const x[3],
+                                     void* const y[3]) {
+    if (!ctx) return SPH_E_ARG;
+    if (!nb || !x || !y) return ctx->fail(SPH_E_ARG, "visc_apply: null argument");
+    if (nb->device != ctx->device) return ctx->fail(SPH_E_ARG, "visc_apply: handle of another device");
+    for (int c = 0; c < 3; ++c)
+        if (!x[c] || !y[c]) return ctx->fail(SPH_E_ARG, "visc_apply: null vector");
+    SPH_TRY(check_particles(ctx, nb, p));
+    SPH_TRY(check_params(ctx, params, prec));
+    if (prec == SPH_F64) return apply_entry<double>(ctx, nb, p, params, x, y);
+    return apply_entry<float>(ctx, nb, p, params, x, y);
+}

@@ -1,0 +1,188 @@
+// Operator kernels y = A x, optionally fused with the inner products the
+// solver needs from the same pass (the paper's gemv plus dot products,
+// appendix "Implementation notes").
+#pragma once
+
+#include <cmath>
+
+#include "sph_device.hpp"
+
+namespace sph {
+
+// Inner products produced per block alongside y = A x:
+//   kDotA1     3 partials: w . y            (delta = r0hat . A p)
+//   kDotA2     6 partials: x . y, y . y     (r* . A r*,  A r* . A r*)
+//   kDotA2Std  9 partials: as kDotA2 plus x . x (textbook half-step check)
+//   kDotResid  3 partials: y . y with y = b - A x in FP64 (true residual)
+enum DotMode { kDotNone = 0, kDotA1 = 1, kDotA2 = 2, kDotA2Std = 3, kDotResid = 4 };
+
+template <int MODE>
+struct DotK {
+    static constexpr int K = MODE == kDotA1 ? 3 : MODE == kDotA2 ? 6 : MODE == kDotA2Std ? 9
+                             : MODE == kDotResid ? 3 : 1;
+};
+
+template <typename T, int MODE>
+__device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V3<T> yv, V3<T> wv) {
+    if constexpr (MODE == kDotA1) {
+        acc[0] += (double)wv.x * (double)yv.x;
+        acc[1] += (double)wv.y * (double)yv.y;
+        acc[2] += (double)wv.z * (double)yv.z;
+    } else if constexpr (MODE == kDotA2 || MODE == kDotA2Std) {
+        acc[0] += (double)xs.x * (double)yv.x;
+        acc[1] += (double)xs.y * (double)yv.y;
+        acc[2] += (double)xs.z * (double)yv.z;
+        acc[3] += (double)yv.x * (double)yv.x;
+        acc[4] += (double)yv.y * (double)yv.y;
+        acc[5] += (double)yv.z * (double)yv.z;
+        if constexpr (MODE == kDotA2Std) {
+            acc[6] += (double)xs.x * (double)xs.x;
+            acc[7] += (double)xs.y * (double)xs.y;
+            acc[8] += (double)xs.z * (double)xs.z;
+        }
+    }
+}
+
+// Cached operator: y_r = dg_r x_r + sum_k coef[r,k] x[col[r,k]].
+// One wavefront per 64-row slice; each block takes a contiguous range of
+// slices (XCD-aware order) and its 4 waves interleave over it.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
+                                                       const T* __restrict__ x, T* __restrict__ y,
+                                                       const T* __restrict__ w, double* __restrict__ part) {
+    if (halt && *halt) return;
+    constexpr int K = DotK<MODE>::K;
+    __shared__ double lds[K * (kBlock / kWave)];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t spb = ceil_div(A.nslices, (int64_t)gridDim.x);
+    const int64_t s0 = bid * spb;
+    const int64_t s1 = min(s0 + spb, A.nslices);
+    for (int64_t s = s0 + wid; s < s1; s += kBlock / kWave) {
+        const int64_t row = s * kWave + lane;
+        if (row >= n) continue;
+        const int64_t base = A.sl_ptr[s] + lane;
+        const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
+        const int32_t* __restrict__ cp = A.cols + base;
+        const T* __restrict__ wp = A.coef + base;
+        T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll 4
+        for (int32_t k = 0; k < width; ++k) {
+            const int32_t c = cp[(int64_t)k * kWave];
+            const T cf = wp[(int64_t)k * kWave];
+            const V3<T> xv = ld3(x, c);
+            a0 = fma_t(cf, xv.x, a0);
+            a1 = fma_t(cf, xv.y, a1);
+            a2 = fma_t(cf, xv.z, a2);
+        }
+        const V3<T> xs = ld3(x, row);
+        const T d = A.dg[row];
+        V3<T> yv;
+        yv.x = fma_t(d, xs.x, a0);
+        yv.y = fma_t(d, xs.y, a1);
+        yv.z = fma_t(d, xs.z, a2);
+        st3(y, row, yv);
+        if constexpr (MODE != kDotNone) {
+            V3<T> wv{};
+            if constexpr (MODE == kDotA1) wv = ld3(w, row);
+            accumulate_dots<T, MODE>(acc, xs, yv, wv);
+        }
+    }
+    if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);
+}
+
+// One row of the operator evaluated from positions in FP64 (the paper's
+// matrix-free gemv): returns (A x)_b, or (D^-1 A x)_b with Jacobi.
+template <typename T>
+__device__ inline void row_apply_otf(const NbrView& nv, const PartView& pv, const OpParams& op,
+                                     const T* __restrict__ x, int32_t b, double (&y)[3]) {
+    const V3<T> xb = ld3(x, b);
+    y[0] = (double)xb.x;
+    y[1] = (double)xb.y;
+    y[2] = (double)xb.z;
+    if (pv.type[b] == SPH_FLUID) {
+        double sw = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for_each_neighbor(nv, b, [&](int32_t a, double r2) {
+            const double wgt = pair_w(pv, nv.g, op.avg, b, a, r2);
+            const V3<T> xa = ld3(x, a);
+            sw += wgt;
+            s0 += wgt * (double)xa.x;
+            s1 += wgt * (double)xa.y;
+            s2 += wgt * (double)xa.z;
+        });
+        const double diag = 1.0 + op.dt * sw;
+        y[0] = diag * y[0] - op.dt * s0;
+        y[1] = diag * y[1] - op.dt * s1;
+        y[2] = diag * y[2] - op.dt * s2;
+        if (op.jacobi) {
+            y[0] /= diag;
+            y[1] /= diag;
+            y[2] /= diag;
+        }
+    } else if (op.wall == SPH_WALL_DUMMY) {
+        double sW = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for_each_neighbor(nv, b, [&](int32_t a, double r2) {
+            if (pv.type[a] != SPH_FLUID) return;
+            const double W = pair_W(nv.g, r2);
+            const V3<T> xa = ld3(x, a);
+            sW += W;
+            s0 += W * (double)xa.x;
+            s1 += W * (double)xa.y;
+            s2 += W * (double)xa.z;
+        });
+        if (sW > 0.0) {
+            y[0] += s0 / sW;
+            y[1] += s1 / sW;
+            y[2] += s2 / sW;
+        }
+    }
+}
+
+// On-the-fly operator over rows in cell order; with kDotResid it writes
+// y = b64 - A x instead (FP64 residual rounded to T) and its squared norm.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
+                                                      OpParams op, const T* __restrict__ x, T* __restrict__ y,
+                                                      const T* __restrict__ w, const double* __restrict__ b64,
+                                                      double* __restrict__ part) {
+    if (halt && *halt) return;
+    constexpr int K = DotK<MODE>::K;
+    __shared__ double lds[K * (kBlock / kWave)];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(nv.n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb;
+    const int64_t r1 = min(r0 + rpb, nv.n);
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        double yv[3];
+        row_apply_otf<T>(nv, pv, op, x, (int32_t)r, yv);
+        if constexpr (MODE == kDotResid) {
+            const V3<double> bb = ld3(b64, r);
+            yv[0] = bb.x - yv[0];
+            yv[1] = bb.y - yv[1];
+            yv[2] = bb.z - yv[2];
+            acc[0] += yv[0] * yv[0];
+            acc[1] += yv[1] * yv[1];
+            acc[2] += yv[2] * yv[2];
+        }
+        V3<T> out;
+        out.x = (T)yv[0];
+        out.y = (T)yv[1];
+        out.z = (T)yv[2];
+        st3(y, r, out);
+        if constexpr (MODE != kDotNone && MODE != kDotResid) {
+            V3<T> wv{};
+            if constexpr (MODE == kDotA1) wv = ld3(w, r);
+            accumulate_dots<T, MODE>(acc, ld3(x, r), out, wv);
+        }
+    }
+    if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);
+}
+
+}  // namespace sph

@@ -1,0 +1,764 @@
+// BiCGSTAB for the three systems A V = B sharing one matrix
+// (Section "Restructuring the stabilized biconjugate gradient method").
+//
+// One iteration is five kernels:
+//   P   p = r + beta p - alpha' A p      (robust; textbook: p = r + beta (p - omega v))
+//   A1  A p, and partials of delta = r0hat . A p
+//   S   s = r - alpha A p                 (the paper's r_star)
+//   A2  A s, and partials of s . A s, A s . A s (and s . s for the textbook check)
+//   K3  x = x + alpha p + omega s, r = s - omega A s, partials of r0hat . r and r . r
+// Every kernel that needs a scalar reduces the previous kernel's per-block
+// partials itself, in a fixed order, so each block derives the same scalars
+// without a host round trip or an extra launch; block 0 also records them in
+// the control block.  All inner products and scalars are FP64.
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+
+#include "operator_kernels.hpp"
+
+namespace sph {
+
+constexpr int kKp = 9;  // partials per block of the close-out / initial-residual kernels
+
+// Initial residual: r = b - A x0 (ax = null: x0 = 0), r0hat = r; partials of
+// r0hat . r, r . r and b . b.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(int64_t n, const T* __restrict__ b, const T* __restrict__ ax,
+                                                 T* __restrict__ r, T* __restrict__ rh0, double* __restrict__ part) {
+    __shared__ double lds[kKp * (kBlock / kWave)];
+    double acc[kKp];
+#pragma unroll
+    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const V3<T> bv = ld3(b, i);
+        V3<T> rv = bv;
+        if (ax) {
+            const V3<T> av = ld3(ax, i);
+            rv.x = bv.x - av.x;
+            rv.y = bv.y - av.y;
+            rv.z = bv.z - av.z;
+        }
+        st3(r, i, rv);
+        st3(rh0, i, rv);
+        const double q[3] = {(double)rv.x, (double)rv.y, (double)rv.z};
+        const double bb[3] = {(double)bv.x, (double)bv.y, (double)bv.z};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] += q[c] * q[c];
+            acc[3 + c] += q[c] * q[c];
+            acc[6 + c] += bb[c] * bb[c];
+        }
+    }
+    write_partials<kKp>(acc, lds, part);
+}
+
+// Scalars of the p update of iteration `it`, i.e. the outcome of iteration
+// j = it - 1 (or of the initial residual when it == 1).
+struct PScalars {
+    double g[3], ap[3], bt[3], rr[3], tau2[3], bb[3];
+    int32_t state[3], stall[3], stall0[3];
+    int32_t reason;
+    int32_t nonfinite;
+};
+
+__device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const SolveConst& sc,
+                                 const double (&red)[kKp], PScalars& o) {
+    const int32_t j = it - 1;
+    const int prev = j & 1;
+    o.nonfinite = 0;
+    int any_prog = 0;
+    for (int c = 0; c < 3; ++c) {
+        const double g = red[c];
+        const double rr = red[3 + c];
+        double tau2, bb;
+        int stall = 0, st0 = 0;
+        double ap = 0.0, bt = 0.0;
+        if (it == 1) {
+            bb = red[6 + c];
+            tau2 = sc.tol2 * bb;
+            if (tau2 < sc.floor_) tau2 = sc.floor_;
+            if (!finite_d(bb)) o.nonfinite = 1;
+        } else {
+            bb = ctl->bb[c];
+            tau2 = ctl->tau2[c];
+            if (sc.variant == SPH_ROBUST) {
+                // alpha'_j = gamma_{j+1}/delta_j, beta_j = alpha'_j/omega_j
+                stall = ctl->stallB[prev][c];
+                if (!stall) {
+                    ap = g / ctl->delta[prev][c];
+                    if (!finite_d(ap)) ap = 0.0;
+                    bt = ap / ctl->omega[prev][c];
+                    if (!finite_d(bt)) bt = 0.0;
+                }
+                if (g == 0.0) stall = 1;
+            } else {
+                // beta_{j+1} = (gamma_{j+1}/gamma_j)(alpha_j/omega_j)
+                stall = ctl->stallB[prev][c];
+                const double gp = ctl->gam[prev][c], al = ctl->alpha[prev][c], om = ctl->omega[prev][c];
+                if (gp != 0.0 && om != 0.0) bt = (g / gp) * (al / om);
+                if (!finite_d(bt)) bt = 0.0;
+            }
+        }
+        if (it > 1 && ctl->restart_iter == j && ctl->restart[c]) {
+            // restarted from the true residual: fresh direction
+            o.g[c] = ctl->gam_restart[c];
+            o.rr[c] = ctl->rr_restart[c];
+            o.ap[c] = 0.0;
+            o.bt[c] = 0.0;
+            o.state[c] = o.rr[c] < tau2 ? SPH_CONVERGED : SPH_PROGRESSING;
+        } else {
+            o.g[c] = g;
+            o.rr[c] = rr;
+            o.ap[c] = ap;
+            o.bt[c] = bt;
+            o.state[c] = rr < tau2 ? SPH_CONVERGED : (stall ? SPH_STATE_STALLED : SPH_PROGRESSING);
+        }
+        if (sc.variant == SPH_STANDARD && o.g[c] == 0.0) st0 = 1;  // breakdown of iteration it
+        o.stall[c] = stall;
+        o.stall0[c] = st0;
+        o.tau2[c] = tau2;
+        o.bb[c] = bb;
+        any_prog |= (o.state[c] == SPH_PROGRESSING);
+    }
+    int32_t reason = 0;
+    if (!any_prog || o.nonfinite) reason |= kHaltNoProg;
+    if (sc.true_res_period > 0 && j > 0 && j % sc.true_res_period == 0 && ctl->checked_iter != j)
+        reason |= kHaltPeriodic;
+    if (j >= sc.max_iter) reason |= kHaltMaxIter;
+    o.reason = reason;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                 const double* __restrict__ part, int32_t nblk, int64_t n,
+                                                 const T* __restrict__ r, T* __restrict__ p,
+                                                 const T* __restrict__ ap, double* __restrict__ hist,
+                                                 int32_t* __restrict__ stallhist) {
+    if (ctl->halt) return;
+    __shared__ double lds[kKp * (kBlock / kWave)];
+    double red[kKp];
+    reduce_partials<kKp>(part, nblk, red, lds);
+    PScalars s;
+    p_scalars(ctl, it, sc, red, s);
+    const int32_t j = it - 1;
+    const int cur = it & 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            ctl->gam[cur][c] = s.g[c];
+            ctl->alphap[cur][c] = s.ap[c];
+            ctl->beta[cur][c] = s.bt[c];
+            ctl->stall0[cur][c] = s.stall0[c];
+            ctl->rr[c] = s.rr[c];
+            ctl->state[c] = s.state[c];
+            if (it == 1) {
+                ctl->tau2[c] = s.tau2[c];
+                ctl->bb[c] = s.bb[c];
+            }
+            if (j < sc.hist_cap) {
+                hist[3 * j + c] = s.rr[c];
+                stallhist[3 * j + c] = s.stall[c];
+            }
+        }
+        if (s.nonfinite) ctl->nonfinite = 1;
+        ctl->halt_reason = s.reason;
+        ctl->iter = s.reason ? j : it;
+        if (s.reason) ctl->halt = 1;
+    }
+    if (s.reason) return;
+    // body: p update; a zero coefficient skips its vector
+    const bool use_p = s.bt[0] != 0.0 || s.bt[1] != 0.0 || s.bt[2] != 0.0;
+    const bool use_ap = sc.variant == SPH_ROBUST ? (s.ap[0] != 0.0 || s.ap[1] != 0.0 || s.ap[2] != 0.0) : use_p;
+    double om[3];
+    for (int c = 0; c < 3; ++c) om[c] = sc.variant == SPH_ROBUST ? 0.0 : (it > 1 ? ctl->omega[j & 1][c] : 1.0);
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const V3<T> rv = ld3(r, i);
+        V3<T> pv{}, av{};
+        if (use_p) pv = ld3(p, i);
+        if (use_ap) av = ld3(ap, i);
+        T o[3] = {rv.x, rv.y, rv.z};
+        const T pp[3] = {pv.x, pv.y, pv.z};
+        const T aa[3] = {av.x, av.y, av.z};
+        for (int c = 0; c < 3; ++c) {
+            if (sc.variant == SPH_ROBUST) {
+                if (s.bt[c] != 0.0) o[c] = o[c] + (T)s.bt[c] * pp[c];
+                if (s.ap[c] != 0.0) o[c] = o[c] - (T)s.ap[c] * aa[c];
+            } else if (s.bt[c] != 0.0) {
+                o[c] = o[c] + (T)s.bt[c] * (pp[c] - (T)om[c] * aa[c]);
+            }
+        }
+        V3<T> out;
+        out.x = o[0];
+        out.y = o[1];
+        out.z = o[2];
+        st3(p, i, out);
+    }
+}
+
+// alpha_i = gamma_i/delta_i, then s = r - alpha A p.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_supd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                 const double* __restrict__ part, int32_t nblk, int64_t n,
+                                                 const T* __restrict__ r, const T* __restrict__ ap,
+                                                 T* __restrict__ s) {
+    if (ctl->halt) return;
+    __shared__ double lds[3 * (kBlock / kWave)];
+    double red[3];
+    reduce_partials<3>(part, nblk, red, lds);
+    const int cur = it & 1;
+    double al[3];
+    int32_t stall[3];
+    for (int c = 0; c < 3; ++c) {
+        double d = red[c];
+        if (it == sc.force_stall_iter && c == sc.force_stall_comp) d = 0.0;
+        red[c] = d;
+        stall[c] = ctl->stall0[cur][c];
+        double a = 0.0;
+        if (d != 0.0 && finite_d(d)) a = ctl->gam[cur][c] / d;
+        if (!finite_d(a) || d == 0.0 || !finite_d(d)) {
+            a = 0.0;
+            stall[c] = 1;
+        }
+        al[c] = a;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            ctl->delta[cur][c] = red[c];
+            ctl->alpha[cur][c] = al[c];
+            ctl->stallA[cur][c] = stall[c];
+        }
+    }
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    const T a0 = (T)al[0], a1 = (T)al[1], a2 = (T)al[2];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const V3<T> rv = ld3(r, i);
+        const V3<T> av = ld3(ap, i);
+        V3<T> o;
+        o.x = rv.x - a0 * av.x;
+        o.y = rv.y - a1 * av.y;
+        o.z = rv.z - a2 * av.z;
+        st3(s, i, o);
+    }
+}
+
+// omega_i = (s . A s)/(A s . A s); x = x + alpha p + omega s; r = s - omega A s;
+// partials of r0hat . r and r . r.
+template <typename T, int KA>
+__global__ __launch_bounds__(kBlock) void k_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                  const double* __restrict__ part, int32_t nblk, int64_t n,
+                                                  T* __restrict__ x, const T* __restrict__ p,
+                                                  const T* __restrict__ s, const T* __restrict__ as,
+                                                  T* __restrict__ r, const T* __restrict__ rh0,
+                                                  double* __restrict__ part_out) {
+    if (ctl->halt) return;
+    __shared__ double lds[kKp * (kBlock / kWave)];
+    double red[KA];
+    reduce_partials<KA>(part, nblk, red, lds);
+    const int cur = it & 1;
+    double om[3], al[3];
+    int32_t stall[3];
+    for (int c = 0; c < 3; ++c) {
+        const double ts = red[c], tt = red[3 + c];
+        double w = 0.0;
+        if (tt != 0.0) w = ts / tt;
+        if (!finite_d(w)) w = 0.0;
+        stall[c] = ctl->stallA[cur][c] | (w == 0.0 ? 1 : 0);
+        if constexpr (KA == 9) {
+            if (red[6 + c] < ctl->tau2[c]) w = 0.0;  // r_star already meets the threshold
+        }
+        om[c] = w;
+        al[c] = ctl->alpha[cur][c];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            ctl->omega[cur][c] = om[c];
+            ctl->stallB[cur][c] = stall[c];
+        }
+    }
+    double acc[kKp];
+#pragma unroll
+    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    const T A[3] = {(T)al[0], (T)al[1], (T)al[2]};
+    const T W[3] = {(T)om[0], (T)om[1], (T)om[2]};
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const V3<T> xv = ld3(x, i), pv = ld3(p, i), sv = ld3(s, i), av = ld3(as, i), hv = ld3(rh0, i);
+        const T xx[3] = {xv.x, xv.y, xv.z}, pp[3] = {pv.x, pv.y, pv.z}, ss[3] = {sv.x, sv.y, sv.z};
+        const T aa[3] = {av.x, av.y, av.z}, hh[3] = {hv.x, hv.y, hv.z};
+        T xo[3], ro[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T t = xx[c] + A[c] * pp[c];
+            xo[c] = t + W[c] * ss[c];
+            ro[c] = ss[c] - W[c] * aa[c];
+            acc[c] += (double)hh[c] * (double)ro[c];
+            acc[3 + c] += (double)ro[c] * (double)ro[c];
+        }
+        st3(x, i, V3<T>{xo[0], xo[1], xo[2]});
+        st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
+    }
+    write_partials<kKp>(acc, lds, part_out);
+}
+
+// Residual check, step 2 (one block): decide which converged components
+// failed the FP64 true residual and must restart.
+__global__ __launch_bounds__(kBlock) void k_check_decide(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                         int32_t nblk) {
+    __shared__ double lds[3 * (kBlock / kWave)];
+    double red[3];
+    reduce_partials<3>(part, nblk, red, lds);
+    if (threadIdx.x != 0) return;
+    ctl->n_true_checks += 1;
+    for (int c = 0; c < 3; ++c) {
+        ctl->trr[c] = red[c];
+        int rs = 0;
+        if (ctl->state[c] == SPH_CONVERGED && !(red[c] < ctl->tau2[c])) {
+            if (ctl->n_restart[c] < kMaxRestarts) {
+                rs = 1;
+                ctl->state[c] = SPH_PROGRESSING;
+                ctl->n_restart[c] += 1;
+                ctl->n_replaced += 1;
+            } else {
+                ctl->state[c] = SPH_STATE_STALLED;
+            }
+        }
+        ctl->restart[c] = rs;
+    }
+    ctl->restart_iter = ctl->iter;
+    ctl->checked_iter = ctl->iter;
+}
+
+// Residual check, step 3: r = r0hat = r_true for restarted components, and
+// partials of the new r0hat . r, r . r.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_check_copy(const Ctl* __restrict__ ctl, int64_t n,
+                                                       const T* __restrict__ rt, T* __restrict__ r,
+                                                       T* __restrict__ rh0, double* __restrict__ part) {
+    __shared__ double lds[6 * (kBlock / kWave)];
+    double acc[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = 0.0;
+    const int rs[3] = {ctl->restart[0], ctl->restart[1], ctl->restart[2]};
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    if (rs[0] | rs[1] | rs[2]) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const V3<T> tv = ld3(rt, i);
+            V3<T> rv = ld3(r, i), hv = ld3(rh0, i);
+            if (rs[0]) { rv.x = tv.x; hv.x = tv.x; }
+            if (rs[1]) { rv.y = tv.y; hv.y = tv.y; }
+            if (rs[2]) { rv.z = tv.z; hv.z = tv.z; }
+            st3(r, i, rv);
+            st3(rh0, i, hv);
+            const double q[3] = {(double)rv.x, (double)rv.y, (double)rv.z};
+            for (int c = 0; c < 3; ++c) {
+                acc[c] += q[c] * q[c];
+                acc[3 + c] += q[c] * q[c];
+            }
+        }
+    }
+    write_partials<6>(acc, lds, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                         int32_t nblk) {
+    __shared__ double lds[6 * (kBlock / kWave)];
+    double red[6];
+    reduce_partials<6>(part, nblk, red, lds);
+    if (threadIdx.x != 0) return;
+    for (int c = 0; c < 3; ++c) {
+        ctl->gam_restart[c] = red[c];
+        ctl->rr_restart[c] = red[3 + c];
+    }
+}
+
+// Final FP64 true residual, reduced into ctl->trr (one block).
+__global__ __launch_bounds__(kBlock) void k_final_trr(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                      int32_t nblk) {
+    __shared__ double lds[3 * (kBlock / kWave)];
+    double red[3];
+    reduce_partials<3>(part, nblk, red, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) ctl->trr[c] = red[c];
+}
+
+__global__ void k_ctl_init(Ctl* ctl) {
+    int32_t* w = reinterpret_cast<int32_t*>(ctl);
+    for (size_t i = threadIdx.x; i < sizeof(Ctl) / sizeof(int32_t); i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->checked_iter = -1;
+        ctl->restart_iter = -1;
+    }
+}
+
+// rhs in caller order -> b64 = D^-1 B in FP64 and b = rounded copy, cell order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prep_rhs(int64_t n, const int32_t* __restrict__ perm,
+                                                     const T* __restrict__ b0, const T* __restrict__ b1,
+                                                     const T* __restrict__ b2, const double* __restrict__ diag64,
+                                                     int32_t jacobi, double* __restrict__ b64,
+                                                     T* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = perm[i];
+    double v[3] = {(double)b0[o], (double)b1[o], (double)b2[o]};
+    if (jacobi) {
+        const double d = diag64[i];
+        for (int c = 0; c < 3; ++c) v[c] = v[c] / d;
+    }
+    st3(b64, i, V3<double>{v[0], v[1], v[2]});
+    st3(b, i, V3<T>{(T)v[0], (T)v[1], (T)v[2]});
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+namespace {
+
+sph_status read_ctl(sph_ctx* ctx, const Ctl* d, Ctl* h) {
+    SPH_HIP(hipMemcpyAsync(h, d, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    SPH_HIP(hipStreamSynchronize(ctx->stream));
+    return SPH_OK;
+}
+
+template <typename T>
+struct Solver {
+    sph_ctx* ctx;
+    const sph_nbr* nb;
+    PartView pv;
+    OpParams op;
+    int32_t mode;
+    Sell<T> sell{};
+    const double* diag64 = nullptr;
+    Launch L;
+    T *b, *x, *r, *rh0, *p, *ap, *s, *as, *tmp;
+    double* b64;
+    double *pa1, *pa2, *pk3, *pchk;
+    Ctl* ctl;
+    double* hist;
+    int32_t* stallhist;
+    SolveConst sc;
+    int32_t launches = 0;
+    // profiling of the A r_star launches: (iteration, issue round, event pair)
+    bool profile = false;
+    int32_t round = 0;
+    struct Rec {
+        int32_t it, round, ev;
+    };
+    std::vector<Rec> recs;
+    std::vector<int32_t> round_end;  // last executed iteration of each round
+
+    sph_status prof_event(int idx, hipEvent_t* out) {
+        while ((int)ctx->prof_ev.size() <= idx) {
+            hipEvent_t e;
+            SPH_HIP(hipEventCreate(&e));
+            ctx->prof_ev.push_back(e);
+        }
+        *out = ctx->prof_ev[idx];
+        return SPH_OK;
+    }
+
+    // y = A x fused with the dot products of mode MODE
+    template <int MODE>
+    void apply(const int32_t* halt, const T* xin, T* yout, const T* w, double* part) {
+        if (mode == SPH_OP_CACHED)
+            hipLaunchKernelGGL((k_apply_sell<T, MODE>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream, halt,
+                               L.n, sell, xin, yout, w, part);
+        else
+            hipLaunchKernelGGL((k_apply_otf<T, MODE>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream, halt,
+                               nb->view(), pv, op, xin, yout, w, (const double*)nullptr, part);
+        ++launches;
+    }
+
+    sph_status iteration(int32_t it) {
+        const int32_t* halt = &ctl->halt;
+        hipLaunchKernelGGL(k_pupd<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc, pk3,
+                           L.grid_stream, L.n, r, p, ap, hist, stallhist);
+        apply<kDotA1>(halt, p, ap, rh0, pa1);
+        hipLaunchKernelGGL(k_supd<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc, pa1,
+                           L.grid_apply, L.n, r, ap, s);
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (profile) {
+            const int k = (int)recs.size();
+            SPH_TRY(prof_event(2 * k, &ev0));
+            SPH_TRY(prof_event(2 * k + 1, &ev1));
+            recs.push_back(Rec{it, round, k});
+            SPH_HIP(hipEventRecord(ev0, ctx->stream));
+        }
+        if (sc.variant == SPH_STANDARD) {
+            apply<kDotA2Std>(halt, s, as, nullptr, pa2);
+            if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
+            hipLaunchKernelGGL((k_close<T, 9>), dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc,
+                               pa2, L.grid_apply, L.n, x, p, s, as, r, rh0, pk3);
+        } else {
+            apply<kDotA2>(halt, s, as, nullptr, pa2);
+            if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
+            hipLaunchKernelGGL((k_close<T, 6>), dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc,
+                               pa2, L.grid_apply, L.n, x, p, s, as, r, rh0, pk3);
+        }
+        launches += 3;
+        return SPH_OK;
+    }
+
+    // FP64 true residual of the current x into tmp, partials into pchk.
+    void true_residual() {
+        hipLaunchKernelGGL((k_apply_otf<T, kDotResid>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
+                           (const int32_t*)nullptr, nb->view(), pv, op, x, tmp, (const T*)nullptr,
+                           (const double*)b64, pchk);
+        ++launches;
+    }
+
+    void check() {
+        true_residual();
+        hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kBlock), 0, ctx->stream, ctl, pchk, L.grid_apply);
+        hipLaunchKernelGGL(k_check_copy<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, L.n, tmp, r,
+                           rh0, pchk + 3 * (size_t)L.grid_apply);
+        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctl,
+                           pchk + 3 * (size_t)L.grid_apply, L.grid_stream);
+        launches += 3;
+    }
+};
+
+template <typename T>
+sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part, const sph_visc_params* vp,
+                      int32_t prec, const void* const rhs[3], void* const xout[3], const sph_solve_opts* o,
+                      sph_solve_report* rep) {
+    Solver<T> S;
+    S.ctx = ctx;
+    S.nb = nb;
+    S.mode = vp->op_mode;
+    S.op = OpParams{vp->dt, vp->wall, vp->avg, vp->jacobi ? 1 : 0};
+    const int64_t n = nb->n;
+    S.L = make_launch(n);
+    const Launch& L = S.L;
+    hipEvent_t e0 = ctx->ev[0], e1 = ctx->ev[1], e2 = ctx->ev[2];
+    SPH_HIP(hipEventRecord(e0, ctx->stream));
+
+    SPH_TRY(gather_props(ctx, nb, part, &S.pv));
+    ++S.launches;
+    S.profile = o->profile != 0;
+    if (S.mode == SPH_OP_CACHED) {
+        SPH_TRY(build_sell<T>(ctx, nb, S.pv, S.op, &S.sell, &S.diag64, &rep->mat_nnz, &rep->mat_slots));
+        S.launches += 6;
+    } else {
+        SPH_TRY(row_diag64(ctx, nb, S.pv, S.op, &S.diag64));
+        ++S.launches;
+    }
+    const size_t v3 = (size_t)n * 3;
+    SPH_TRY(ctx->ensure_t(kVecB, v3, &S.b));
+    SPH_TRY(ctx->ensure_t(kVecX, v3, &S.x));
+    SPH_TRY(ctx->ensure_t(kVecR, v3, &S.r));
+    SPH_TRY(ctx->ensure_t(kVecRh0, v3, &S.rh0));
+    SPH_TRY(ctx->ensure_t(kVecP, v3, &S.p));
+    SPH_TRY(ctx->ensure_t(kVecAp, v3, &S.ap));
+    SPH_TRY(ctx->ensure_t(kVecS, v3, &S.s));
+    SPH_TRY(ctx->ensure_t(kVecAs, v3, &S.as));
+    SPH_TRY(ctx->ensure_t(kVecTmp, v3, &S.tmp));
+    SPH_TRY(ctx->ensure_t(kB64, v3, &S.b64));
+    SPH_TRY(ctx->ensure_t(kPartA1, (size_t)L.grid_apply * 3, &S.pa1));
+    SPH_TRY(ctx->ensure_t(kPartA2, (size_t)L.grid_apply * 9, &S.pa2));
+    SPH_TRY(ctx->ensure_t(kPartK3, (size_t)L.grid_stream * kKp, &S.pk3));
+    SPH_TRY(ctx->ensure_t(kPartChk, (size_t)L.grid_apply * 3 + (size_t)L.grid_stream * 6, &S.pchk));
+    SPH_TRY(ctx->ensure_t(kCtl, 1, &S.ctl));
+    const int32_t hist_rows = o->max_iter + 1;
+    SPH_TRY(ctx->ensure_t(kHist, (size_t)hist_rows * 3, &S.hist));
+    SPH_TRY(ctx->ensure_t(kStallHist, (size_t)hist_rows * 3, &S.stallhist));
+
+    S.sc.tol2 = o->tol * o->tol;
+    S.sc.floor_ = o->floor >= 0.0 ? o->floor : (prec == SPH_F32 ? (double)FLT_MIN : DBL_MIN);
+    S.sc.max_iter = o->max_iter;
+    S.sc.variant = o->variant;
+    S.sc.true_res_period = o->true_res_period;
+    S.sc.force_stall_iter = o->force_stall_iter;
+    S.sc.force_stall_comp = o->force_stall_comp;
+    S.sc.hist_cap = hist_rows;
+
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, ctx->stream, S.ctl);
+    hipLaunchKernelGGL(k_prep_rhs<T>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
+                       nb->perm, (const T*)rhs[0], (const T*)rhs[1], (const T*)rhs[2], S.diag64, S.op.jacobi,
+                       S.b64, S.b);
+    S.launches += 2;
+    SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
+    SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
+    const T* ax = nullptr;
+    if (o->x0_given) {
+        SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
+        S.template apply<kDotNone>(nullptr, S.x, S.tmp, nullptr, nullptr);
+        ax = S.tmp;
+        ++S.launches;
+    } else {
+        SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
+    }
+    hipLaunchKernelGGL(k_init<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, n, S.b, ax, S.r, S.rh0,
+                       S.pk3);
+    ++S.launches;
+    SPH_LAUNCHED("solve setup");
+    SPH_HIP(hipEventRecord(e1, ctx->stream));
+
+    // Iterate.  The host issues iterations in batches and reads the device
+    // halt flag one batch behind; kernels issued after a halt return at once.
+    struct Mail {
+        int32_t halt, reason;  // Ctl::halt and Ctl::halt_reason, adjacent
+    };
+    Mail* mail = static_cast<Mail*>(ctx->host_mail);
+    const int kmax = o->poll_every > 0 ? o->poll_every : 16;
+    const int32_t last_it = o->max_iter + 1;  // P of this iteration always halts
+    int32_t j = 0;
+    Ctl hctl;
+    for (;;) {
+        int32_t it = j + 1;
+        int k = std::min(2, kmax);
+        int pend[2], npend = 0, batch = 0;
+        bool halted = false;
+        while (!halted) {
+            if (it <= last_it) {
+                for (int q = 0; q < k && it <= last_it; ++q) SPH_TRY(S.iteration(it++));
+                SPH_LAUNCHED("iteration kernels");
+                const int slot = batch++ & 1;
+                SPH_HIP(hipMemcpyAsync(&mail[slot], &S.ctl->halt, sizeof(Mail), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+                SPH_HIP(hipEventRecord(ctx->ev[3 + slot], ctx->stream));
+                pend[npend++] = slot;
+                k = std::min(2 * k, kmax);
+            }
+            // read the older poll once two are in flight (or nothing is left to issue)
+            if (npend == 2 || (it > last_it && npend > 0)) {
+                const int slot = pend[0];
+                pend[0] = pend[1];
+                --npend;
+                SPH_HIP(hipEventSynchronize(ctx->ev[3 + slot]));
+                if (mail[slot].halt) halted = true;
+            } else if (it > last_it && npend == 0) {
+                halted = true;
+            }
+        }
+        SPH_HIP(hipStreamSynchronize(ctx->stream));
+        SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
+        if (hctl.nonfinite) return ctx->fail(SPH_E_NONFINITE, "visc_solve: non-finite right-hand side");
+        if (!hctl.halt) return ctx->fail(SPH_E_HIP, "visc_solve: iteration issue ended without a halt");
+        j = hctl.iter;
+        S.round_end.push_back(j);
+        ++S.round;
+        if (hctl.halt_reason & (kHaltNoProg | kHaltPeriodic)) {
+            S.check();
+            SPH_LAUNCHED("residual check");
+            SPH_HIP(hipStreamSynchronize(ctx->stream));
+            SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
+        }
+        bool any_prog = false;
+        for (int c = 0; c < 3; ++c) any_prog |= hctl.state[c] == SPH_PROGRESSING;
+        if (!any_prog || j >= o->max_iter) break;
+        SPH_HIP(hipMemsetAsync(&S.ctl->halt, 0, sizeof(int32_t), ctx->stream));
+    }
+    // final FP64 true residual for the report
+    S.true_residual();
+    hipLaunchKernelGGL(k_final_trr, dim3(1), dim3(kBlock), 0, ctx->stream, S.ctl, S.pchk, L.grid_apply);
+    ++S.launches;
+    SPH_TRY(scatter_vec3<T>(ctx, nb, S.x, xout));
+    ++S.launches;
+    SPH_LAUNCHED("solve finish");
+    SPH_HIP(hipEventRecord(e2, ctx->stream));
+    SPH_HIP(hipStreamSynchronize(ctx->stream));
+    SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
+
+    rep->iters = hctl.iter;
+    int any_prog = 0, any_stall = 0;
+    for (int c = 0; c < 3; ++c) {
+        rep->state[c] = hctl.state[c];
+        rep->rr[c] = hctl.rr[c];
+        rep->bb[c] = hctl.bb[c];
+        rep->tau2[c] = hctl.tau2[c];
+        rep->true_rr[c] = hctl.trr[c];
+        any_prog |= hctl.state[c] == SPH_PROGRESSING;
+        any_stall |= hctl.state[c] == SPH_STATE_STALLED;
+    }
+    rep->n_true_checks = hctl.n_true_checks;
+    rep->n_replaced = hctl.n_replaced;
+    const int32_t rows = std::min(hctl.iter + 1, hist_rows);
+    std::vector<int32_t> sh((size_t)rows * 3);
+    SPH_HIP(hipMemcpyAsync(sh.data(), S.stallhist, sizeof(int32_t) * sh.size(), hipMemcpyDeviceToHost, ctx->stream));
+    SPH_HIP(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < 3; ++c) {
+        int32_t cnt = 0;
+        for (int32_t q = 1; q < rows; ++q) cnt += sh[(size_t)q * 3 + c];
+        rep->stall_count[c] = cnt;
+    }
+    rep->history_len = 0;
+    if (rep->history && rep->history_cap > 0) {
+        const int32_t hl = std::min(rows, rep->history_cap);
+        SPH_HIP(hipMemcpyAsync(rep->history, S.hist, sizeof(double) * (size_t)hl * 3, hipMemcpyDeviceToHost, ctx->stream));
+        SPH_HIP(hipStreamSynchronize(ctx->stream));
+        rep->history_len = hl;
+    }
+    float ms_setup = 0.f, ms_iter = 0.f;
+    SPH_HIP(hipEventElapsedTime(&ms_setup, e0, e1));
+    SPH_HIP(hipEventElapsedTime(&ms_iter, e1, e2));
+    rep->setup_ms = ms_setup;
+    rep->iterate_ms = ms_iter;
+    rep->launches = S.launches;
+    if (S.profile) {
+        double tot = 0.0;
+        int32_t cnt = 0;
+        for (const auto& r : S.recs) {
+            if (r.round >= (int32_t)S.round_end.size() || r.it > S.round_end[r.round]) continue;  // returned at once
+            float ms = 0.f;
+            SPH_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * r.ev], ctx->prof_ev[2 * r.ev + 1]));
+            tot += ms;
+            ++cnt;
+        }
+        rep->apply_ms = tot;
+        rep->apply_launches = cnt;
+    }
+    rep->status = any_prog ? SPH_NOT_CONVERGED : (any_stall ? SPH_STALLED : SPH_OK);
+    return (sph_status)rep->status;
+}
+
+}  // namespace
+
+extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_domain* dom,
+                                     const sph_particles* p, const sph_visc_params* params, int32_t prec,
+                                     const void* const rhs[3], void* const x[3], const sph_solve_opts* opts,
+                                     sph_solve_report* report) {
+    if (!ctx) return SPH_E_ARG;
+    if (!rhs || !x || !opts || !report) return ctx->fail(SPH_E_ARG, "visc_solve: null argument");
+    for (int c = 0; c < 3; ++c)
+        if (!rhs[c] || !x[c]) return ctx->fail(SPH_E_ARG, "visc_solve: null vector");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 0 || opts->max_iter > 100000000)
+        return ctx->fail(SPH_E_ARG, "visc_solve: tol or max_iter out of range");
+    if (opts->variant != SPH_ROBUST && opts->variant != SPH_STANDARD)
+        return ctx->fail(SPH_E_ARG, "visc_solve: variant");
+    if (opts->true_res_period < 0) return ctx->fail(SPH_E_ARG, "visc_solve: true_res_period < 0");
+    sph_nbr* own = nullptr;
+    if (!nb) {
+        if (!dom) return ctx->fail(SPH_E_ARG, "visc_solve: neither neighbour handle nor domain");
+        SPH_TRY(sph_build_neighbors(ctx, p, dom, &own));
+        nb = own;
+    }
+    if (nb->device != ctx->device) return ctx->fail(SPH_E_ARG, "visc_solve: handle of another device");
+    sph_status st = check_particles(ctx, nb, p);
+    if (st == SPH_OK) st = check_params(ctx, params, prec);
+    if (st == SPH_OK) {
+        double* hist_keep = report->history;
+        int32_t cap_keep = report->history_cap;
+        std::memset(report, 0, sizeof(*report));
+        report->history = hist_keep;
+        report->history_cap = cap_keep;
+        st = prec == SPH_F64 ? solve_impl<double>(ctx, nb, p, params, prec, rhs, x, opts, report)
+                             : solve_impl<float>(ctx, nb, p, params, prec, rhs, x, opts, report);
+    }
+    if (own) sph_neighbors_free(own);
+    return st;
+}

@@ -1,0 +1,225 @@
+// Device-side building blocks: kernel function, neighbour traversal, pair
+// coefficients, vector access and wavefront/block reductions.
+#pragma once
+
+#include "sph_internal.hpp"
+
+namespace sph {
+
+// Wendland psi_{3,1} kernel of radius 2 (Section "Smoothing kernel choice"):
+// W(r,h) = w(r/h)/h^3 with w(q) = 21/(16 pi) (1 - q/2)^4 (2q + 1), and
+// F(r,h) = (1/r) dW/dr = f(r/h)/h^5 with f(q) = 105/(128 pi) (q - 2)^3, both
+// zero for q >= 2.
+__device__ inline double wendland_w(double q) {
+    if (!(q < 2.0)) return 0.0;
+    double a = 1.0 - 0.5 * q;
+    return 21.0 / (16.0 * kPi) * (a * a * a * a) * (2.0 * q + 1.0);
+}
+
+__device__ inline double wendland_f(double q) {
+    if (!(q < 2.0)) return 0.0;
+    double a = q - 2.0;
+    return 105.0 / (128.0 * kPi) * (a * a * a);
+}
+
+// Displacement on one axis, minimum image on periodic axes.  Rounded exactly
+// like the neighbour predicate everywhere in the library (contraction off).
+__device__ inline double disp(double xb, double xa, double period) {
+    double d = xb - xa;
+    if (period > 0.0) d = d - period * rint(d / period);
+    return d;
+}
+
+// 2 * mean viscosity: arithmetic (mu_a + mu_b), harmonic 4 mu_a mu_b/(mu_a + mu_b)
+// (Section "Discretized equations").
+__device__ inline double two_mubar(double ma, double mb, int avg) {
+    if (avg == SPH_AVG_HARMONIC) {
+        double s = ma + mb;
+        return s > 0.0 ? 4.0 * (ma * mb) / s : 0.0;
+    }
+    return ma + mb;
+}
+
+// Distinct cells of the {c-1, c, c+1} block along one axis (periodic axes
+// with fewer than three cells visit each of their cells once).
+__device__ inline int axis_cells(int32_t c, int32_t n, int32_t per, int32_t (&out)[3]) {
+    if (per) {
+        if (n >= 3) {
+            out[0] = c > 0 ? c - 1 : n - 1;
+            out[1] = c;
+            out[2] = c < n - 1 ? c + 1 : 0;
+            return 3;
+        }
+        for (int i = 0; i < n; ++i) out[i] = i;
+        return n;
+    }
+    int m = 0;
+    for (int d = -1; d <= 1; ++d)
+        if (c + d >= 0 && c + d < n) out[m++] = c + d;
+    return m;
+}
+
+// Calls f(a, r2) for every neighbour a of sorted particle `row` (a != row,
+// r2 = |r_row - r_a|^2 < (2h)^2), visiting the 3x3x3 cell block around the
+// particle's cell as at most 9 runs of consecutive cells along x (a wrapped
+// periodic x adds a second run).
+template <class F>
+__device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) {
+    const Grid& g = nv.g;
+    const double xb = nv.px[row], yb = nv.py[row], zb = nv.pz[row];
+    const int32_t c = nv.scell[row];
+    const int32_t nx = g.nc[0], ny = g.nc[1];
+    const int32_t cx = c % nx;
+    const int32_t cy = (c / nx) % ny;
+    const int32_t cz = c / (nx * ny);
+    int32_t zs[3], ys[3];
+    const int nzs = axis_cells(cz, g.nc[2], g.per[2], zs);
+    const int nys = axis_cells(cy, ny, g.per[1], ys);
+    // x runs [a0, b0] and [a1, b1] (second run empty unless x wraps)
+    int32_t a0, b0, a1 = 1, b1 = 0;
+    if (g.per[0] && nx >= 3) {
+        if (cx == 0) { a0 = 0; b0 = 1; a1 = nx - 1; b1 = nx - 1; }
+        else if (cx == nx - 1) { a0 = nx - 2; b0 = nx - 1; a1 = 0; b1 = 0; }
+        else { a0 = cx - 1; b0 = cx + 1; }
+    } else if (g.per[0]) {
+        a0 = 0; b0 = nx - 1;
+    } else {
+        a0 = cx > 0 ? cx - 1 : 0;
+        b0 = cx < nx - 1 ? cx + 1 : nx - 1;
+    }
+    for (int iz = 0; iz < nzs; ++iz) {
+        for (int iy = 0; iy < nys; ++iy) {
+            const int32_t base = (zs[iz] * ny + ys[iy]) * nx;
+            for (int run = 0; run < 2; ++run) {
+                const int32_t xa = run == 0 ? a0 : a1;
+                const int32_t xe = run == 0 ? b0 : b1;
+                if (xa > xe) continue;
+                const int32_t beg = nv.cell_start[base + xa];
+                const int32_t end = nv.cell_start[base + xe + 1];
+                for (int32_t a = beg; a < end; ++a) {
+                    if (a == row) continue;
+                    double dx = disp(xb, nv.px[a], g.period[0]);
+                    double dy = disp(yb, nv.py[a], g.period[1]);
+                    double dz = disp(zb, nv.pz[a], g.period[2]);
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < g.cut2) f(a, r2);
+                }
+            }
+        }
+    }
+}
+
+// Pair weight w_ba = -2 mubar m_a F(r)/(rho_a rho_b) >= 0 of row b and
+// neighbour a (eq. kab, diffusive sign).
+__device__ inline double pair_w(const PartView& pv, const Grid& g, int avg, int32_t b,
+                                int32_t a, double r2) {
+    double q = sqrt(r2) / g.h;
+    double h2 = g.h * g.h;
+    double F = wendland_f(q) / (h2 * h2 * g.h);
+    double tm = two_mubar(pv.mu[a], pv.mu[b], avg);
+    return -(tm * pv.mass[a] * F) / (pv.rho[a] * pv.rho[b]);
+}
+
+// Kernel value W_ba of the dummy-wall rows (eq. dummyvel).
+__device__ inline double pair_W(const Grid& g, double r2) {
+    double q = sqrt(r2) / g.h;
+    return wendland_w(q) / (g.h * g.h * g.h);
+}
+
+// ---------------------------------------------------------------------------
+// Interleaved 3-vectors (x, y, z of one particle adjacent in memory).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct V3 {
+    T x, y, z;
+};
+
+template <typename T>
+__device__ inline V3<T> ld3(const T* __restrict__ v, int64_t i) {
+    V3<T> r;
+    r.x = v[3 * i + 0];
+    r.y = v[3 * i + 1];
+    r.z = v[3 * i + 2];
+    return r;
+}
+
+template <typename T>
+__device__ inline void st3(T* __restrict__ v, int64_t i, V3<T> a) {
+    v[3 * i + 0] = a.x;
+    v[3 * i + 1] = a.y;
+    v[3 * i + 2] = a.z;
+}
+
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Reductions.  Every sum is taken in a fixed order that depends only on the
+// launch geometry, so repeated runs give bitwise identical scalars.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Block-wide sum of K values per thread; result valid in every thread.
+// `lds` must hold K * (blockDim.x / 64) doubles.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k * nw + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[k * nw + w];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Sums K partials per block written by a previous kernel:
+// part[blk * K + k], blk < nblk.  Every block computes the same result.
+template <int K>
+__device__ inline void reduce_partials(const double* __restrict__ part, int nblk, double (&out)[K],
+                                       double* lds) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] += part[(int64_t)b * K + k];
+    }
+    block_sum<K>(out, lds);
+}
+
+// Writes the block's K sums as its partials (thread 0).
+template <int K>
+__device__ inline void write_partials(double (&v)[K], double* lds, double* __restrict__ part) {
+    block_sum<K>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[(int64_t)blockIdx.x * K + k] = v[k];
+    }
+}
+
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// XCD-aware block order: the hardware hands consecutive block ids to the 8
+// XCDs in turn; remap so that each XCD works on one contiguous share of the
+// rows and its L2 keeps the neighbour data of that share.
+__device__ inline int32_t xcd_block(int32_t b, int32_t nblk) {
+    const int32_t per = nblk / kNumXcd;
+    if (per == 0 || nblk % kNumXcd) return b;
+    return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+}  // namespace sph

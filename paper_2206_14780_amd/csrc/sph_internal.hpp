@@ -1,0 +1,249 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per block of the row kernels (4 waves)
+constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Cell grid of a neighbour handle.  Cells are at least 2h wide on every axis,
+// so all neighbours of a particle lie in the 3x3x3 block of cells around it.
+// ---------------------------------------------------------------------------
+struct Grid {
+    int32_t nc[3];      // cells per axis
+    double org[3];      // lower corner (domain lo)
+    double cs[3];       // cell side
+    double period[3];   // period on periodic axes, 0 elsewhere
+    int32_t per[3];     // periodic flags
+    double h;           // smoothing length
+    double cut2;        // (2h)^2, the neighbour predicate's bound
+};
+
+// Device view of a neighbour handle (cell-sorted positions).
+struct NbrView {
+    int64_t n;
+    Grid g;
+    const int32_t* cell_start;  // [ncell + 1]
+    const int32_t* scell;       // cell id of each sorted particle
+    const double* px;           // sorted positions
+    const double* py;
+    const double* pz;
+};
+
+// Per-particle operator data in cell order.
+struct PartView {
+    const double* mass;
+    const double* rho;
+    const double* mu;
+    const uint8_t* type;
+};
+
+struct OpParams {
+    double dt;
+    int32_t wall;
+    int32_t avg;
+    int32_t jacobi;
+};
+
+// Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).
+// Entry k of row r = s*64 + l lives at sl_ptr[s] + k*64 + l; rows shorter
+// than their slice are padded with (col = r, coef = 0).
+template <typename T>
+struct Sell {
+    int64_t nslices;
+    const int64_t* sl_ptr;  // [nslices + 1]
+    const int32_t* cols;
+    const T* coef;
+    const T* dg;            // diagonal of the (scaled) matrix, per row
+};
+
+// ---------------------------------------------------------------------------
+// Solver control block in device memory.  Fields indexed [2] are double
+// buffered by iteration parity: the kernel that writes slot it&1 never reads
+// it, so every block of a kernel sees the values of earlier kernels only.
+// ---------------------------------------------------------------------------
+enum HaltReason : int32_t { kHaltNoProg = 1, kHaltPeriodic = 2, kHaltMaxIter = 4 };
+
+// A component that the recursive residual calls converged but the FP64 true
+// residual rejects is restarted at most this many times; after that it is
+// reported stalled (its precision cannot reach the tolerance).
+constexpr int32_t kMaxRestarts = 3;
+
+struct Ctl {
+    // written by the p-update kernel (block 0)
+    double gam[2][3];     // gamma_i = r0hat . r_{i-1}
+    double alphap[2][3];  // alpha'_{i-1}
+    double beta[2][3];    // beta_{i-1}
+    int32_t stall0[2][3]; // textbook variant: gamma_i == 0
+    double rr[3];         // r.r of the last completed iteration
+    double bb[3];
+    double tau2[3];
+    int32_t state[3];
+    int32_t iter;         // iterations started
+    int32_t halt;         // nonzero: every iteration kernel returns at once
+    int32_t halt_reason;
+    // written by the s-update kernel (block 0)
+    double delta[2][3];
+    double alpha[2][3];
+    int32_t stallA[2][3];
+    // written by the close-out kernel (block 0)
+    double omega[2][3];
+    int32_t stallB[2][3];
+    // written by the residual-check kernels
+    double trr[3];
+    double gam_restart[3];
+    double rr_restart[3];
+    int32_t restart[3];
+    int32_t n_restart[3];
+    int32_t restart_iter;
+    int32_t checked_iter;
+    int32_t n_true_checks;
+    int32_t n_replaced;
+    int32_t nonfinite;
+};
+
+// Constants of one solve, passed by value to the iteration kernels.
+struct SolveConst {
+    double tol2;
+    double floor_;
+    int32_t max_iter;
+    int32_t variant;
+    int32_t true_res_period;
+    int32_t force_stall_iter;
+    int32_t force_stall_comp;
+    int32_t hist_cap;      // rows of the device history arrays
+};
+
+// Launch geometry of the row kernels.
+struct Launch {
+    int64_t n;
+    int32_t grid_apply;    // blocks of the operator kernels
+    int32_t grid_stream;   // blocks of the streaming kernels
+};
+
+Launch make_launch(int64_t n);
+
+// ---------------------------------------------------------------------------
+// Device workspace: named, monotonically growing allocations of a context.
+// ---------------------------------------------------------------------------
+enum Slot : int {
+    kMass, kRho, kMu, kType, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg,
+    kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
+    kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
+    kApplyIn, kApplyOut, kExportCnt, kNnzCount, kNumSlots
+};
+
+}  // namespace sph
+
+struct sph_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void* ws[sph::kNumSlots] = {};
+    size_t ws_bytes[sph::kNumSlots] = {};
+    void* host_mail = nullptr;   // pinned host mailbox for polling the control block
+    hipEvent_t ev[5] = {};        // 0-2: solve timing, 3-4: halt polls
+    std::vector<hipEvent_t> prof_ev;  // pairs bracketing profiled launches
+
+    sph_status fail(sph_status s, const std::string& what);
+    sph_status hip_fail(hipError_t e, const char* what);
+    // Ensure workspace slot `slot` holds at least `bytes`; on success *out
+    // receives the device pointer.
+    sph_status ensure(int slot, size_t bytes, void** out);
+    template <typename P>
+    sph_status ensure_t(int slot, size_t count, P** out) {
+        void* v = nullptr;
+        sph_status s = ensure(slot, count * sizeof(P), &v);
+        *out = static_cast<P*>(v);
+        return s;
+    }
+};
+
+struct sph_nbr {
+    int32_t device = 0;
+    int64_t n = 0;
+    int64_t ncell = 0;
+    sph::Grid g{};
+    int32_t* cell_start = nullptr;
+    int32_t* scell = nullptr;
+    int32_t* perm = nullptr;    // sorted -> original
+    int32_t* iperm = nullptr;   // original -> sorted
+    double* px = nullptr;
+    double* py = nullptr;
+    double* pz = nullptr;
+    int64_t nnz = -1;           // pair count, computed on demand
+
+    sph::NbrView view() const {
+        sph::NbrView v;
+        v.n = n;
+        v.g = g;
+        v.cell_start = cell_start;
+        v.scell = scell;
+        v.px = px;
+        v.py = py;
+        v.pz = pz;
+        return v;
+    }
+};
+
+#define SPH_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ctx->hip_fail(e_, #call);         \
+    } while (0)
+
+#define SPH_TRY(expr)                                                  \
+    do {                                                               \
+        sph_status s_ = (expr);                                        \
+        if (s_ != SPH_OK) return s_;                                   \
+    } while (0)
+
+#define SPH_LAUNCHED(what)                                             \
+    do {                                                               \
+        hipError_t e_ = hipGetLastError();                             \
+        if (e_ != hipSuccess) return ctx->hip_fail(e_, what);          \
+    } while (0)
+
+namespace sph {
+
+// Exclusive scan of `n` values into out[0..n] (out[n] = total), on the stream.
+sph_status scan_i32(sph_ctx* ctx, const int32_t* in, int32_t* out, int64_t n);
+sph_status scan_i64(sph_ctx* ctx, const int64_t* in, int64_t* out, int64_t n);
+
+// Operator pieces (operator.hip).
+sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out);
+template <typename T>
+sph_status gather_vec3(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst);
+template <typename T>
+sph_status scatter_vec3(sph_ctx* ctx, const sph_nbr* nb, const T* src, void* const dst[3]);
+// Builds the cached matrix; *nnz / *slots (host, optional) receive the
+// off-diagonal entry count and the stored slot count.
+template <typename T>
+sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
+                      Sell<T>* out, const double** diag64, int64_t* nnz = nullptr,
+                      int64_t* slots = nullptr);
+template <typename T>
+sph_status apply_plain(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
+                       int mode, const Sell<T>* sell, const T* x, T* y);
+sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
+                      const double** diag64);
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace sph
+
+// Argument checks shared by the entry points.
+sph_status check_particles(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p);
+sph_status check_params(sph_ctx* ctx, const sph_visc_params* v, int32_t prec);

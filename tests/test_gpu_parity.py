@@ -1,0 +1,224 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Neighbour lists bit-exact; operator within a
+rounding bound derived from the arithmetic; solutions within 1e-10 (FP64
+path) and 1e-5 (FP32 path) relative L2."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_14780_amd import sph as S
+from paper_2206_14780_amd import workloads as W
+
+from gpu_util import (F32_U, F64_U, GpuCase, apply_bound, oracle_op, rel_l2, small_tank, to_np)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return S.Context(0)
+
+
+def _systems():
+    out = [
+        W.with_random_order(W.poiseuille(16, wall=W.WALL_DYNAMIC), 1),
+        W.poiseuille(8, wall=W.WALL_DUMMY),
+        small_tank(seed=3),
+        small_tank(seed=4, n=(7, 5, 4), wall=W.WALL_DYNAMIC, avg=W.AVG_ARITH),
+        W.open_box(n=11, seed=12),
+        W.incline_papanastasiou(n=10, seed=13),
+    ]
+    return out
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_neighbour_lists_bit_exact(ctx, idx):
+    w = _systems()[idx]
+    print(f"[neighbours] {w.name} n={w.n}", flush=True)
+    g = GpuCase(ctx, w)
+    rp, cols = g.export()
+    orp, ocols = O.neighbors(w.pos, w.period, w.h, method="brute" if w.n < 6000 else "grid", lo=w.lo)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(cols, ocols)
+    n, nnz = ctx.sph_neighbors_info(g.nb)
+    assert n == w.n and nnz == len(ocols)
+
+
+def test_neighbours_tiny_and_clamped(ctx):
+    # one particle; two particles across a periodic face; particles outside
+    # the box on a non-periodic axis (binned into the edge cells).
+    rng = np.random.default_rng(0)
+    cases = []
+    p1 = W.Workload("one", np.array([[0.5, 0.5, 0.5]]), np.ones(1), np.ones(1), np.ones(1),
+                    np.zeros(1, np.uint8), np.zeros(3), np.ones(3) * 4, np.array([1, 1, 1]), 0.6,
+                    0.1, 0, 0, np.ones((1, 3)), None, 1e-8)
+    cases.append(p1)
+    p2 = W.Workload("two", np.array([[0.1, 1.0, 1.0], [3.95, 1.2, 1.0]]), np.ones(2), np.ones(2),
+                    np.ones(2), np.zeros(2, np.uint8), np.zeros(3), np.ones(3) * 4,
+                    np.array([1, 0, 0]), 0.6, 0.1, 0, 0, np.ones((2, 3)), None, 1e-8)
+    cases.append(p2)
+    pos = rng.uniform(-2.0, 12.0, size=(700, 3))
+    p3 = W.Workload("clamped", pos, np.ones(700), np.ones(700), np.ones(700),
+                    np.zeros(700, np.uint8), np.zeros(3), np.ones(3) * 10.0, np.array([0, 0, 0]),
+                    0.7, 0.1, 0, 0, np.ones((700, 3)), None, 1e-8)
+    cases.append(p3)
+    for w in cases:
+        g = GpuCase(ctx, w)
+        rp, cols = g.export()
+        orp, ocols = O.neighbors(w.pos, w.period, w.h, method="brute")
+        assert np.array_equal(rp, orp) and np.array_equal(cols, ocols), w.name
+
+
+@pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_F32])
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+@pytest.mark.parametrize("jacobi", [True, False])
+@pytest.mark.parametrize("idx", [0, 2, 3, 5])
+def test_operator_parity(ctx, prec, op_mode, jacobi, idx):
+    w = _systems()[idx]
+    print(f"[apply] {w.name} prec={prec} mode={op_mode} jacobi={jacobi}", flush=True)
+    g = GpuCase(ctx, w)
+    X = np.random.default_rng(idx).normal(size=(w.n, 3))
+    if prec == S.SPH_F32:
+        X = X.astype(np.float32).astype(np.float64)
+    Y = g.apply(X, prec, jacobi=jacobi, op_mode=op_mode)
+    op = oracle_op(w, jacobi=jacobi)
+    Yo = op.apply(X)
+    D = oracle_op(w, jacobi=False, nbr=(op.row_ptr, op.cols)).diag()
+    if prec == S.SPH_F64:
+        bound = apply_bound(D, X, F64_U, jacobi)
+    elif op_mode == S.SPH_OP_CACHED:
+        bound = apply_bound(D, X, F32_U, jacobi)
+    else:  # coefficients and sums in FP64, output rounded once
+        bound = apply_bound(D, X, F64_U, jacobi) + F32_U * np.abs(Yo).max(axis=1)
+    err = np.abs(Y - Yo).max(axis=1)
+    assert np.all(err <= bound), (err / bound).max()
+
+
+def test_operator_dummy_wall_and_average_variants(ctx):
+    w = small_tank(seed=9)
+    g = GpuCase(ctx, w)
+    X = np.random.default_rng(2).normal(size=(w.n, 3))
+    for wall in (W.WALL_DYNAMIC, W.WALL_DUMMY):
+        for avg in (W.AVG_ARITH, W.AVG_HARMONIC):
+            Y = g.apply(X, S.SPH_F64, jacobi=False, wall=wall, avg=avg)
+            op = oracle_op(w, jacobi=False, wall=wall, avg=avg)
+            Yo = op.apply(X)
+            bound = apply_bound(op.diag(), X, F64_U, False)
+            assert np.all(np.abs(Y - Yo).max(axis=1) <= bound)
+
+
+@pytest.mark.parametrize("wall", [W.WALL_DYNAMIC, W.WALL_DUMMY])
+@pytest.mark.parametrize("variant", [S.SPH_ROBUST, S.SPH_STANDARD])
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+def test_solve_fp64_poiseuille(ctx, wall, variant, op_mode):
+    # 16^3 Poiseuille channel, dt nu/dp^2 = 10, rhs = dt g: FP64 path within
+    # 1e-10 of the oracle (both solved to 1e-12), same iteration count.
+    w = W.poiseuille(16, wall=wall)
+    print(f"[solve64] {w.name} variant={variant} mode={op_mode}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-12, variant=variant, op_mode=op_mode)
+    Xo, ro, ho = O.solve(oracle_op(w), w.rhs, tol=1e-12, variant=variant)
+    assert rep["status"] == S.SPH_OK and rep["state"] == [S.SPH_CONVERGED] * 3
+    assert abs(rep["iters"] - ro["iters"]) <= 1
+    assert rel_l2(X, Xo) < 1e-10
+    h = np.array(rep["history"])
+    n = min(len(h), len(ho), 6)
+    # summation-order differences (~1e-16) grow through the Krylov recurrences
+    assert np.allclose(h[:n, 0], ho[:n, 0], rtol=1e-7, atol=0), np.abs(h[:n, 0] / ho[:n, 0] - 1).max()
+
+
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+@pytest.mark.parametrize("seed,wall", [(21, W.WALL_DUMMY), (22, W.WALL_DYNAMIC)])
+def test_solve_fp32_ragged_tank(ctx, op_mode, seed, wall):
+    # N = 396 (ragged slice), viscosity over 3 decades, dt nu_max/dp^2 = 50,
+    # harmonic mean.  FP32 vectors and operator, FP64 scalars, eps = 1e-6,
+    # against the oracle at 1e-12: relative L2 error below 1e-5.
+    w = small_tank(seed=seed, wall=wall)
+    print(f"[solve32] {w.name} seed={seed} mode={op_mode}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F32, tol=1e-6, op_mode=op_mode)
+    Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-12)
+    assert rep["status"] == S.SPH_OK
+    assert rel_l2(X, Xo) < 1e-5
+    for c in range(3):
+        assert rep["true_rr"][c] < rep["tau2"][c] * 1.0001 or rep["bb"][c] == 0.0
+
+
+def test_solve_fp64_ragged_tank_both_variants(ctx):
+    w = small_tank(seed=31)
+    g = GpuCase(ctx, w)
+    for variant in (S.SPH_ROBUST, S.SPH_STANDARD):
+        X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-12, variant=variant)
+        Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-12, variant=variant)
+        assert rep["status"] == 0 and rel_l2(X, Xo) < 1e-10
+        assert abs(rep["iters"] - ro["iters"]) <= 2
+
+
+def test_solve_warm_start_and_zero_components(ctx):
+    w = W.poiseuille(8, wall=W.WALL_DUMMY)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-10)
+    assert rep["state"] == [S.SPH_CONVERGED] * 3
+    assert np.all(X[:, 1:] == 0.0)          # zero rhs components: converged with no work
+    assert rep["history"][0][1] == 0.0 and rep["tau2"][1] == np.finfo(np.float64).tiny
+    X2, rep2 = g.solve(w.rhs, S.SPH_F64, X0=X, tol=1e-8)
+    assert rep2["iters"] == 0 and np.array_equal(X, X2)
+
+
+def test_forced_stall_matches_oracle_and_spares_other_components(ctx):
+    w = small_tank(seed=41, dt_nu=30.0)
+    g = GpuCase(ctx, w)
+    X0, r0 = g.solve(w.rhs, S.SPH_F64, tol=1e-10)
+    X1, r1 = g.solve(w.rhs, S.SPH_F64, tol=1e-10, force_stall=(2, 1))
+    Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-10, force_stall=(2, 1))
+    assert r0["stall_count"] == [0, 0, 0] and r1["stall_count"][1] >= 1
+    assert r1["stall_count"] == ro["stall_count"]
+    h0, h1 = np.array(r0["history"]), np.array(r1["history"])
+    n = min(len(h0), len(h1))
+    assert np.array_equal(h0[:n, 0], h1[:n, 0]) and np.array_equal(h0[:n, 2], h1[:n, 2])
+    assert rel_l2(X1, Xo) < 1e-8
+
+
+def test_error_paths(ctx):
+    w = small_tank(seed=51)
+    g = GpuCase(ctx, w)
+    B = w.rhs.copy()
+    B[5, 1] = np.nan
+    with pytest.raises(S.SphError) as e:
+        g.solve(B, S.SPH_F64)
+    assert e.value.status == S.SPH_E_NONFINITE
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-14, max_iter=2)
+    assert rep["status"] == S.SPH_NOT_CONVERGED and rep["iters"] == 2
+    assert len(rep["history"]) == 3 and np.all(np.isfinite(X))
+    Xo, ro, ho = O.solve(oracle_op(w), w.rhs, tol=1e-14, max_iter=2)
+    assert rel_l2(X, Xo) < 1e-12
+
+
+def test_single_particle(ctx):
+    w = W.Workload("one", np.array([[0.5, 0.5, 0.5]]), np.ones(1), np.ones(1), np.ones(1),
+                   np.zeros(1, np.uint8), np.zeros(3), np.ones(3) * 4, np.array([1, 1, 1]), 0.6,
+                   0.1, 0, 0, np.array([[1.0, -2.0, 0.0]]), None, 1e-8)
+    g = GpuCase(ctx, w)
+    for prec in (S.SPH_F64, S.SPH_F32):
+        X, rep = g.solve(w.rhs, prec)
+        assert rep["status"] == 0 and np.array_equal(X, w.rhs)
+
+
+def test_true_residual_checks_match_oracle(ctx):
+    w = small_tank(seed=61)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-10, true_res_period=1)
+    Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-10, true_res_period=1)
+    assert rep["n_replaced"] == 0
+    assert abs(rep["n_true_checks"] - ro["n_true_checks"]) <= 1
+    assert rel_l2(X, Xo) < 1e-9
+
+
+def test_deterministic(ctx):
+    w = small_tank(seed=71, n=(9, 8, 7))
+    g = GpuCase(ctx, w)
+    a, ra = g.solve(w.rhs, S.SPH_F32, tol=1e-6)
+    b, rb = g.solve(w.rhs, S.SPH_F32, tol=1e-6)
+    assert np.array_equal(a, b) and ra["history"] == rb["history"]

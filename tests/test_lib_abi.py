@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every function include/sph.h
+declares, and the ctypes mirror of each struct has the C layout.  CPU only:
+no compute calls."""
+import ctypes as C
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2206_14780_amd import sph as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(S.LIB_PATH):
+        from paper_2206_14780_amd import build
+        build.build()
+    return C.CDLL(S.LIB_PATH)
+
+
+def test_header_declares_the_entry_points():
+    names = S.header_functions()
+    for f in ("sph_build_neighbors", "sph_visc_apply", "sph_visc_solve", "sph_create",
+              "sph_destroy", "sph_neighbors_export", "sph_neighbors_free", "sph_status_str"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in S.header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    lib.sph_status_str.restype = C.c_char_p
+    lib.sph_status_str.argtypes = [C.c_int]
+    assert lib.sph_status_str(0) == b"ok"
+    assert lib.sph_status_str(-5) == b"non-finite input"
+
+
+def test_null_context_is_an_argument_error(lib):
+    lib.sph_visc_solve.restype = C.c_int
+    assert lib.sph_visc_solve(None, None, None, None, None, 0, None, None, None, None) == -1
+    lib.sph_create.restype = C.c_int
+    assert lib.sph_create(None, 0, None) == -1
+
+
+STRUCTS = {
+    "sph_particles": ["n", "x", "y", "z", "mass", "rho", "mu", "type"],
+    "sph_domain": ["lo", "hi", "periodic", "h"],
+    "sph_visc_params": ["dt", "wall", "avg", "jacobi", "op_mode"],
+    "sph_solve_opts": ["tol", "max_iter", "variant", "floor", "true_res_period", "x0_given",
+                       "poll_every", "force_stall_iter", "force_stall_comp", "profile"],
+    "sph_solve_report": ["iters", "status", "state", "stall_count", "rr", "bb", "tau2", "true_rr",
+                         "n_true_checks", "n_replaced", "history", "history_cap", "history_len",
+                         "setup_ms", "iterate_ms", "launches", "mat_nnz", "mat_slots", "apply_ms",
+                         "apply_launches"],
+}
+
+
+def test_ctypes_layout_matches_c():
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', "int main(void){"]
+    for st, fields in STRUCTS.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fields:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.split() for l in out if l.strip())
+    for st, fields in STRUCTS.items():
+        cls = getattr(S, st)
+        assert int(got[st]) == C.sizeof(cls), st
+        for f in fields:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
