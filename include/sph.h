@@ -113,7 +113,13 @@ typedef struct {
  *          component's delta is treated as zero.  -1 = off.
  *   profile: 1 = bracket every executed launch of the second operator kernel
  *          of an iteration (A r_star and its dot products) with HIP events on
- *          the context stream and report their total time (apply_ms). */
+ *          the context stream and report their total time (apply_ms).
+ *   restart_drop: at each periodic true-residual check, a progressing
+ *          component whose true r.r has fallen below restart_drop times its
+ *          r.r at the last (re)start restarts from the true residual
+ *          (r0hat = r = r_true, alpha' = beta = 0).  Keeps the shadow vector
+ *          commensurate with the residual when vectors are FP32.  < 0 selects
+ *          1e-6 (SPH_F32) or 0 = never (SPH_F64). */
 typedef struct {
     double tol;
     int32_t max_iter;
@@ -125,6 +131,7 @@ typedef struct {
     int32_t force_stall_iter;
     int32_t force_stall_comp;
     int32_t profile;
+    double restart_drop;
 } sph_solve_opts;
 
 /* Solve report (host memory).  history, if non-null, is a host buffer of
@@ -140,7 +147,7 @@ typedef struct {
     double tau2[3];
     double true_rr[3];      /* final FP64 (b - A x).(b - A x) of the scaled system */
     int32_t n_true_checks;
-    int32_t n_replaced;
+    int32_t n_replaced;     /* restarts from the true residual (both kinds) */
     double *history;        /* host, may be null */
     int32_t history_cap;
     int32_t history_len;

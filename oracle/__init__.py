@@ -50,8 +50,8 @@ def lib():
         L.orc_assemble_dense.argtypes = [C.POINTER(OrcOp), dp]
         L.orc_bicgstab.restype = C.c_int32
         L.orc_bicgstab.argtypes = [C.POINTER(OrcOp), C.c_int32, C.POINTER(dp), C.POINTER(dp),
-                                   C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_int32,
-                                   C.c_int32, C.POINTER(OrcReport), dp, C.c_int32]
+                                   C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_double,
+                                   C.c_int32, C.c_int32, C.POINTER(OrcReport), dp, C.c_int32]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -197,7 +197,7 @@ class Operator:
 
 
 def solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, variant=ROBUST, floor=DBL_MIN,
-          true_res_period=50, force_stall=None, history_cap=None):
+          true_res_period=50, force_stall=None, history_cap=None, restart_drop=0.0):
     """BiCGSTAB solve of A V = B (three columns) with the oracle.
 
     Returns (X (n,3), report dict, history (len,3) of r.r per iteration)."""
@@ -213,8 +213,8 @@ def solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, variant=ROBUST, fl
     xa = (C.POINTER(C.c_double) * 3)(*[_dp(a) for a in xs])
     fi, fc = force_stall if force_stall is not None else (-1, -1)
     lib().orc_bicgstab(C.byref(op.s), int(variant), ba, xa, float(tol), int(max_iter),
-                       float(floor), int(true_res_period), int(fi), int(fc), C.byref(rep),
-                       _dp(hist), cap)
+                       float(floor), int(true_res_period), float(restart_drop), int(fi), int(fc),
+                       C.byref(rep), _dp(hist), cap)
     report = dict(iters=rep.iters, status=rep.status, state=list(rep.state),
                   stall_count=list(rep.stall_count), rr=list(rep.rr), bb=list(rep.bb),
                   tau2=list(rep.tau2), true_rr=list(rep.true_rr),

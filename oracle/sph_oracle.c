@@ -40,7 +40,10 @@
  *     component is progressing, r_true = b - A x is recomputed; a component
  *     marked converged whose true residual fails the threshold is restarted
  *     from r_true (r0hat = r_true, alpha' = beta = 0) and made progressing;
- *     after three such restarts it is reported stalled instead.
+ *     after three such restarts it is reported stalled instead.  Optionally
+ *     (restart_drop > 0) a progressing component whose true r.r at a periodic
+ *     check has fallen below restart_drop times its r.r at the last (re)start
+ *     restarts the same way.
  *   - textbook variant: when the half-step residual s already meets the
  *     threshold the component takes omega = 0 (x = x + alpha p, r = s).
  */
@@ -515,8 +518,8 @@ static void orc_residual(const orc_op *op, double *const *bh, double *const *x, 
  */
 int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, double *const *x,
                  double tol, int32_t max_iter, double floor_, int32_t true_res_period,
-                 int32_t force_stall_iter, int32_t force_stall_comp, orc_report *rep,
-                 double *history, int32_t history_cap) {
+                 double restart_drop, int32_t force_stall_iter, int32_t force_stall_comp,
+                 orc_report *rep, double *history, int32_t history_cap) {
     int64_t n = op->n;
     memset(rep, 0, sizeof(*rep));
     double *buf = (double *)calloc((size_t)(n > 0 ? n : 1) * 3 * 9, sizeof(double));
@@ -539,6 +542,7 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
 
     double gamma[3], gamma_prev[3], alpha[3], alphap[3], beta[3], omega[3], delta[3], tau2[3], rr[3];
     int state[3], restarts[3] = {0, 0, 0};
+    double rr_ref[3];
     for (int c = 0; c < 3; ++c) {
         rep->bb[c] = orc_dot(n, bh[c], bh[c]);
         if (!orc_finite(rep->bb[c])) {
@@ -555,6 +559,7 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
         tau2[c] = tol * tol * rep->bb[c];
         if (tau2[c] < floor_) tau2[c] = floor_;
         rr[c] = orc_dot(n, r[c], r[c]);
+        rr_ref[c] = rr[c];
         gamma[c] = orc_dot(n, rh0[c], r[c]);
         alphap[c] = 0.0;
         beta[c] = 0.0;
@@ -578,12 +583,19 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
             rep->n_true_checks++;
             orc_residual(op, bh, x, tmp, s);
             for (int c = 0; c < 3; ++c) {
-                if (state[c] != ORC_CONVERGED) continue;
                 double trr = orc_dot(n, tmp[c], tmp[c]);
-                if (!(trr < tau2[c]) && restarts[c] >= ORC_MAX_RESTARTS) {
-                    state[c] = ORC_STALLED; /* precision cannot reach the tolerance */
-                } else if (!(trr < tau2[c])) {
-                    restarts[c]++;
+                int restart = 0;
+                if (state[c] == ORC_CONVERGED && !(trr < tau2[c])) {
+                    if (restarts[c] >= ORC_MAX_RESTARTS) {
+                        state[c] = ORC_STALLED; /* precision cannot reach the tolerance */
+                    } else {
+                        restarts[c]++;
+                        restart = 1;
+                    }
+                } else if (state[c] == ORC_PROGRESSING && trr < restart_drop * rr_ref[c]) {
+                    restart = 1; /* residual far below the shadow vector: fresh start */
+                }
+                if (restart) {
                     memcpy(r[c], tmp[c], sizeof(double) * (size_t)n);
                     memcpy(rh0[c], tmp[c], sizeof(double) * (size_t)n);
                     rr[c] = trr;
@@ -595,7 +607,8 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
                     omega[c] = 1.0;
                     memset(p[c], 0, sizeof(double) * (size_t)n);
                     memset(Ap[c], 0, sizeof(double) * (size_t)n);
-                    state[c] = ORC_PROGRESSING;
+                    state[c] = trr < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+                    rr_ref[c] = trr;
                     rep->n_replaced++;
                 }
             }

@@ -1,6 +1,9 @@
 // The viscous operator A(dt): particle data gathers, the cached sliced-ELL
 // matrix (coefficients evaluated once per call in FP64), and the operator
 // kernels used by sph_visc_apply and the solver.
+#include <algorithm>
+#include <cstdlib>
+
 #include "operator_kernels.hpp"
 
 namespace sph {
@@ -144,14 +147,25 @@ __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslice
 }
 
 // Pass 2: write columns and coefficients.  Coefficients are evaluated in
-// FP64 and rounded once to T.
+// FP64 and rounded once to T (FP32 also keeps the rounding remainder).
+__device__ inline void sell_store(int2* pk, float* lo, int32_t*, float*, int64_t i, int32_t col, double c) {
+    const float hi = (float)c;
+    pk[i] = make_int2(col, __float_as_int(hi));
+    lo[i] = (float)(c - (double)hi);
+}
+__device__ inline void sell_store(int2*, float*, int32_t* cols, double* coef, int64_t i, int32_t col, double c) {
+    cols[i] = col;
+    coef[i] = c;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, OpParams op,
                                                      const double* __restrict__ diag64,
                                                      const double* __restrict__ wsum,
-                                                     const int64_t* __restrict__ sl_ptr,
-                                                     int32_t* __restrict__ cols, T* __restrict__ coef,
-                                                     T* __restrict__ dg, int64_t nslices) {
+                                                     const int64_t* __restrict__ sl_ptr, int2* __restrict__ pk,
+                                                     float* __restrict__ lo, int32_t* __restrict__ cols,
+                                                     T* __restrict__ coef, T* __restrict__ dg,
+                                                     double* __restrict__ rs64, int64_t nslices) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nslices * kWave) return;
     const int64_t s = r / kWave;
@@ -168,28 +182,29 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
             for_each_neighbor(nv, row, [&](int32_t a, double r2) {
                 double aba = -op.dt * pair_w(pv, nv.g, op.avg, row, a, r2);
                 double c = op.jacobi ? aba / D : aba;
-                cols[base + (int64_t)k * kWave] = a;
-                coef[base + (int64_t)k * kWave] = (T)c;
+                sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, a, c);
                 ++k;
             });
-            dg[row] = op.jacobi ? T(1) : (T)D;
+            // row sum: (A 1)_r = 1 (eqs. diag, offdiag), scaled by 1/A_rr with Jacobi
+            const double rs = op.jacobi ? 1.0 / D : 1.0;
+            dg[row] = (T)rs;
+            rs64[row] = rs;
         } else {
             const double sW = wsum[row];
+            double rs = 1.0;
             if (op.wall == SPH_WALL_DUMMY && sW > 0.0) {
                 for_each_neighbor(nv, row, [&](int32_t a, double r2) {
                     if (pv.type[a] != SPH_FLUID) return;
-                    cols[base + (int64_t)k * kWave] = a;
-                    coef[base + (int64_t)k * kWave] = (T)(pair_W(nv.g, r2) / sW);
+                    sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, a, pair_W(nv.g, r2) / sW);
                     ++k;
                 });
+                rs = 2.0;  // 1 + sum_a W_ra / sum_a W_ra (eq. implicit-system-dummy-full)
             }
-            dg[row] = T(1);
+            dg[row] = (T)rs;
+            rs64[row] = rs;
         }
     }
-    for (; k < width; ++k) {
-        cols[base + (int64_t)k * kWave] = pad_col;
-        coef[base + (int64_t)k * kWave] = T(0);
-    }
+    for (; k < width; ++k) sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, pad_col, 0.0);
 }
 
 sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
@@ -234,18 +249,31 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     if (slots_out) *slots_out = nnzp;
     int32_t* cols = nullptr;
     T* coef = nullptr;
+    int2* pk = nullptr;
+    float* lo = nullptr;
     T* dg = nullptr;
-    SPH_TRY(ctx->ensure_t(kCols, (size_t)(nnzp > 0 ? nnzp : 1), &cols));
-    SPH_TRY(ctx->ensure_t(kCoef, (size_t)(nnzp > 0 ? nnzp : 1), &coef));
+    const size_t ns = (size_t)(nnzp > 0 ? nnzp : 1);
+    if constexpr (sizeof(T) == 4) {
+        SPH_TRY(ctx->ensure_t(kPk, ns, &pk));
+        SPH_TRY(ctx->ensure_t(kLo, ns, &lo));
+    } else {
+        SPH_TRY(ctx->ensure_t(kCols, ns, &cols));
+        SPH_TRY(ctx->ensure_t(kCoef, ns, &coef));
+    }
+    double* rs64 = nullptr;
     SPH_TRY(ctx->ensure_t(kDg, n, &dg));
+    SPH_TRY(ctx->ensure_t(kRs64, n, &rs64));
     hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, nb->view(), pv, op, d, ws, ptr, cols, coef, dg, nslices);
+                       ctx->stream, nb->view(), pv, op, d, ws, ptr, pk, lo, cols, coef, dg, rs64, nslices);
     SPH_LAUNCHED("k_row_fill");
     out->nslices = nslices;
     out->sl_ptr = ptr;
+    out->pk = pk;
+    out->lo = lo;
     out->cols = cols;
     out->coef = coef;
     out->dg = dg;
+    out->rs64 = rs64;
     if (diag64) *diag64 = d;
     return SPH_OK;
 }
@@ -255,21 +283,35 @@ template sph_status build_sell<float>(sph_ctx*, const sph_nbr*, const PartView&,
 template sph_status build_sell<double>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&,
                                        Sell<double>*, const double**, int64_t*, int64_t*);
 
+static int32_t env_int(const char* name, int32_t dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    long x = std::strtol(v, nullptr, 10);
+    return x > 0 ? (int32_t)x : dflt;
+}
+
+// Launch geometry of the row kernels.  SPH_APPLY_BLOCK / SPH_APPLY_GRID /
+// SPH_STREAM_BLOCK / SPH_STREAM_GRID override the defaults (tuning sweeps).
 Launch make_launch(int64_t n) {
     Launch L;
     L.n = n;
     const int64_t nslices = ceil_div(n, kWave);
-    // operator kernels: one wavefront per slice at a time, 4 waves per block
-    int64_t ga = ceil_div(nslices, 4 * 2);
-    if (ga > 2048) ga = 2048;
-    if (ga >= 64) ga = (ga / kNumXcd) * kNumXcd;
-    if (ga < 1) ga = 1;
-    int64_t gs = ceil_div(n, (int64_t)kBlock * 4);
-    if (gs > 1024) gs = 1024;
-    if (gs >= 64) gs = (gs / kNumXcd) * kNumXcd;
-    if (gs < 1) gs = 1;
-    L.grid_apply = (int32_t)ga;
-    L.grid_stream = (int32_t)gs;
+    int32_t ba = env_int("SPH_APPLY_BLOCK", 256);
+    ba = std::min(std::max(ba / kWave * kWave, kWave), kMaxBlock);
+    const int64_t wpb = ba / kWave;
+    // about two slices per wave, at most 8192 waves
+    int64_t ga = ceil_div(std::min<int64_t>(ceil_div(nslices, 2), 8192), wpb);
+    ga = env_int("SPH_APPLY_GRID", (int32_t)ga);
+    if (ga >= 64) ga = ga / kNumXcd * kNumXcd;
+    L.grid_apply = (int32_t)std::max<int64_t>(ga, 1);
+    L.block_apply = ba;
+    int32_t bs = env_int("SPH_STREAM_BLOCK", 1024);
+    bs = std::min(std::max(bs / kWave * kWave, kWave), kMaxBlock);
+    int64_t gs = std::min<int64_t>(ceil_div(n, (int64_t)bs * 4), 256);
+    gs = env_int("SPH_STREAM_GRID", (int32_t)gs);
+    if (gs >= 64) gs = gs / kNumXcd * kNumXcd;
+    L.grid_stream = (int32_t)std::max<int64_t>(gs, 1);
+    L.block_stream = bs;
     return L;
 }
 
@@ -278,10 +320,11 @@ sph_status apply_plain(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, cons
                        const Sell<T>* sell, const T* x, T* y) {
     const Launch L = make_launch(nb->n);
     if (mode == SPH_OP_CACHED) {
-        hipLaunchKernelGGL((k_apply_sell<T, kDotNone>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
-                           (const int32_t*)nullptr, nb->n, *sell, x, y, (const T*)nullptr, (double*)nullptr);
+        hipLaunchKernelGGL((k_apply_sell<T, kDotNone>), dim3(L.grid_apply), dim3(L.block_apply), 0, ctx->stream,
+                           (const int32_t*)nullptr, nb->n, *sell, x, y, (const T*)nullptr, (const double*)nullptr,
+                           (double*)nullptr);
     } else {
-        hipLaunchKernelGGL((k_apply_otf<T, kDotNone>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
+        hipLaunchKernelGGL((k_apply_otf<T, kDotNone>), dim3(L.grid_apply), dim3(L.block_apply), 0, ctx->stream,
                            (const int32_t*)nullptr, nb->view(), pv, op, x, y, (const T*)nullptr,
                            (const double*)nullptr, (double*)nullptr);
     }

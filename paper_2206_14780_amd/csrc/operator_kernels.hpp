@@ -13,7 +13,8 @@ namespace sph {
 //   kDotA1     3 partials: w . y            (delta = r0hat . A p)
 //   kDotA2     6 partials: x . y, y . y     (r* . A r*,  A r* . A r*)
 //   kDotA2Std  9 partials: as kDotA2 plus x . x (textbook half-step check)
-//   kDotResid  3 partials: y . y with y = b - A x in FP64 (true residual)
+//   kDotResid  3 partials: y . y with y = b - A x evaluated in FP64 with the
+//              FP64-accurate coefficients (true residual)
 enum DotMode { kDotNone = 0, kDotA1 = 1, kDotA2 = 2, kDotA2Std = 3, kDotResid = 4 };
 
 template <int MODE>
@@ -43,53 +44,144 @@ __device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V
     }
 }
 
-// Cached operator: y_r = dg_r x_r + sum_k coef[r,k] x[col[r,k]].
+// One stored entry of the cached matrix: column and coefficient.
+__device__ inline void sell_ld(const Sell<float>& A, int64_t i, int32_t& c, float& w) {
+    const int2 v = A.pk[i];
+    c = v.x;
+    w = __int_as_float(v.y);
+}
+__device__ inline void sell_ld(const Sell<double>& A, int64_t i, int32_t& c, double& w) {
+    c = A.cols[i];
+    w = A.coef[i];
+}
+
+// Low part of an FP32 coefficient (c64 - (double)hi); FP64 matrices are exact.
+__device__ inline double sell_lo(const Sell<float>& A, int64_t i) { return (double)A.lo[i]; }
+__device__ inline double sell_lo(const Sell<double>&, int64_t) { return 0.0; }
+
+constexpr int kGroup = 8;  // entries per software-pipelined group
+
+// sum_k coef[r,k] (x[col[r,k]] - x_r) for the row of this lane (the operator's
+// difference form: rounding scales with the local variation of x, not with x,
+// so smooth fields keep their accuracy in FP32).  `base` is the lane's first
+// slot, `width` the slice width (uniform across the wave).  The loop is
+// software-pipelined: the gathers of group g are issued before the column and
+// coefficient loads of group g + 1, so the L2 latency of the gathers and the
+// HBM latency of the matrix stream overlap.  RES accumulates in FP64 with the
+// FP64-accurate coefficients.
+template <typename T, bool RES, typename ACC>
+__device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, int32_t row,
+                                const T* __restrict__ x, const V3<T>& xs, ACC& a0, ACC& a1, ACC& a2) {
+    int32_t cc[kGroup];
+    T cw[kGroup];
+    double cl[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+        if (u < width) {
+            sell_ld(A, base + (int64_t)u * kWave, cc[u], cw[u]);
+            cl[u] = RES ? sell_lo(A, base + (int64_t)u * kWave) : 0.0;
+        } else {
+            cc[u] = row;
+            cw[u] = T(0);
+            cl[u] = 0.0;
+        }
+    }
+    for (int32_t k0 = 0; k0 < width; k0 += kGroup) {
+        V3<T> xv[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) xv[u] = ld3(x, cc[u]);
+        int32_t nc[kGroup];
+        T nw[kGroup];
+        double nl[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int32_t k = k0 + kGroup + u;
+            if (k < width) {
+                sell_ld(A, base + (int64_t)k * kWave, nc[u], nw[u]);
+                nl[u] = RES ? sell_lo(A, base + (int64_t)k * kWave) : 0.0;
+            } else {
+                nc[u] = row;
+                nw[u] = T(0);
+                nl[u] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if constexpr (RES) {
+                const double w = (double)cw[u] + cl[u];
+                a0 += w * ((double)xv[u].x - (double)xs.x);
+                a1 += w * ((double)xv[u].y - (double)xs.y);
+                a2 += w * ((double)xv[u].z - (double)xs.z);
+            } else {
+                a0 = fma_t(cw[u], xv[u].x - xs.x, a0);
+                a1 = fma_t(cw[u], xv[u].y - xs.y, a1);
+                a2 = fma_t(cw[u], xv[u].z - xs.z, a2);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            cc[u] = nc[u];
+            cw[u] = nw[u];
+            cl[u] = nl[u];
+        }
+    }
+}
+
+// Cached operator: y_r = rs_r x_r + sum_k coef[r,k] (x[col[r,k]] - x_r).
 // One wavefront per 64-row slice; each block takes a contiguous range of
-// slices (XCD-aware order) and its 4 waves interleave over it.
+// slices (XCD-aware order) and its waves interleave over it.  With kDotResid
+// the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
-                                                       const T* __restrict__ x, T* __restrict__ y,
-                                                       const T* __restrict__ w, double* __restrict__ part) {
+__global__ __launch_bounds__(kMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
+                                                          const T* __restrict__ x, T* __restrict__ y,
+                                                          const T* __restrict__ w, const double* __restrict__ b64,
+                                                          double* __restrict__ part) {
     if (halt && *halt) return;
     constexpr int K = DotK<MODE>::K;
-    __shared__ double lds[K * (kBlock / kWave)];
+    constexpr bool RES = MODE == kDotResid;
+    __shared__ double lds[K * kMaxWaves];
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t spb = ceil_div(A.nslices, (int64_t)gridDim.x);
     const int64_t s0 = bid * spb;
     const int64_t s1 = min(s0 + spb, A.nslices);
-    for (int64_t s = s0 + wid; s < s1; s += kBlock / kWave) {
+    for (int64_t s = s0 + wid; s < s1; s += nw) {
         const int64_t row = s * kWave + lane;
         if (row >= n) continue;
         const int64_t base = A.sl_ptr[s] + lane;
         const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
-        const int32_t* __restrict__ cp = A.cols + base;
-        const T* __restrict__ wp = A.coef + base;
-        T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll 4
-        for (int32_t k = 0; k < width; ++k) {
-            const int32_t c = cp[(int64_t)k * kWave];
-            const T cf = wp[(int64_t)k * kWave];
-            const V3<T> xv = ld3(x, c);
-            a0 = fma_t(cf, xv.x, a0);
-            a1 = fma_t(cf, xv.y, a1);
-            a2 = fma_t(cf, xv.z, a2);
-        }
         const V3<T> xs = ld3(x, row);
-        const T d = A.dg[row];
-        V3<T> yv;
-        yv.x = fma_t(d, xs.x, a0);
-        yv.y = fma_t(d, xs.y, a1);
-        yv.z = fma_t(d, xs.z, a2);
-        st3(y, row, yv);
-        if constexpr (MODE != kDotNone) {
-            V3<T> wv{};
-            if constexpr (MODE == kDotA1) wv = ld3(w, row);
-            accumulate_dots<T, MODE>(acc, xs, yv, wv);
+        if constexpr (RES) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            sell_row<T, true>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
+            const double d = A.rs64[row];
+            const V3<double> bb = ld3(b64, row);
+            const double r0 = bb.x - (d * (double)xs.x + a0);
+            const double r1 = bb.y - (d * (double)xs.y + a1);
+            const double r2 = bb.z - (d * (double)xs.z + a2);
+            acc[0] += r0 * r0;
+            acc[1] += r1 * r1;
+            acc[2] += r2 * r2;
+            st3(y, row, V3<T>{(T)r0, (T)r1, (T)r2});
+        } else {
+            T a0 = T(0), a1 = T(0), a2 = T(0);
+            sell_row<T, false>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
+            const T d = A.dg[row];
+            V3<T> yv;
+            yv.x = fma_t(d, xs.x, a0);
+            yv.y = fma_t(d, xs.y, a1);
+            yv.z = fma_t(d, xs.z, a2);
+            st3(y, row, yv);
+            if constexpr (MODE != kDotNone) {
+                V3<T> wv{};
+                if constexpr (MODE == kDotA1) wv = ld3(w, row);
+                accumulate_dots<T, MODE>(acc, xs, yv, wv);
+            }
         }
     }
     if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);
@@ -145,13 +237,13 @@ __device__ inline void row_apply_otf(const NbrView& nv, const PartView& pv, cons
 // On-the-fly operator over rows in cell order; with kDotResid it writes
 // y = b64 - A x instead (FP64 residual rounded to T) and its squared norm.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
-                                                      OpParams op, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ w, const double* __restrict__ b64,
-                                                      double* __restrict__ part) {
+__global__ __launch_bounds__(kMaxBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
+                                                         OpParams op, const T* __restrict__ x, T* __restrict__ y,
+                                                         const T* __restrict__ w, const double* __restrict__ b64,
+                                                         double* __restrict__ part) {
     if (halt && *halt) return;
     constexpr int K = DotK<MODE>::K;
-    __shared__ double lds[K * (kBlock / kWave)];
+    __shared__ double lds[K * kMaxWaves];
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;

@@ -7,13 +7,15 @@
 //   S   s = r - alpha A p                 (the paper's r_star)
 //   A2  A s, and partials of s . A s, A s . A s (and s . s for the textbook check)
 //   K3  x = x + alpha p + omega s, r = s - omega A s, partials of r0hat . r and r . r
+// plus, every `true_res_period` iterations, the FP64-accurate residual
+// b - A x, whose outcome the next P applies (restart of a component that the
+// recursion calls converged but the true residual does not).
 // Every kernel that needs a scalar reduces the previous kernel's per-block
 // partials itself, in a fixed order, so each block derives the same scalars
 // without a host round trip or an extra launch; block 0 also records them in
 // the control block.  All inner products and scalars are FP64.
 #include <algorithm>
 #include <cfloat>
-#include <chrono>
 
 #include "operator_kernels.hpp"
 
@@ -21,27 +23,22 @@ namespace sph {
 
 constexpr int kKp = 9;  // partials per block of the close-out / initial-residual kernels
 
-// Initial residual: r = b - A x0 (ax = null: x0 = 0), r0hat = r; partials of
-// r0hat . r, r . r and b . b.
+// Initial residual: r = b - A x0 given in `r0` (null: x0 = 0, r = b),
+// r0hat = r; partials of r0hat . r, r . r and b . b.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init(int64_t n, const T* __restrict__ b, const T* __restrict__ ax,
-                                                 T* __restrict__ r, T* __restrict__ rh0, double* __restrict__ part) {
-    __shared__ double lds[kKp * (kBlock / kWave)];
+__global__ __launch_bounds__(kMaxBlock) void k_init(int64_t n, const T* __restrict__ b, const T* __restrict__ r0,
+                                                    T* __restrict__ r, T* __restrict__ rh0,
+                                                    double* __restrict__ part) {
+    __shared__ double lds[kKp * kMaxWaves];
     double acc[kKp];
 #pragma unroll
     for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
-    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const V3<T> bv = ld3(b, i);
-        V3<T> rv = bv;
-        if (ax) {
-            const V3<T> av = ld3(ax, i);
-            rv.x = bv.x - av.x;
-            rv.y = bv.y - av.y;
-            rv.z = bv.z - av.z;
-        }
+        const V3<T> rv = r0 ? ld3(r0, i) : bv;
         st3(r, i, rv);
         st3(rh0, i, rv);
         const double q[3] = {(double)rv.x, (double)rv.y, (double)rv.z};
@@ -59,17 +56,19 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, const T* __restrict_
 // Scalars of the p update of iteration `it`, i.e. the outcome of iteration
 // j = it - 1 (or of the initial residual when it == 1).
 struct PScalars {
-    double g[3], ap[3], bt[3], rr[3], tau2[3], bb[3];
-    int32_t state[3], stall[3], stall0[3];
+    double g[3], ap[3], bt[3], rr[3], tau2[3], bb[3], trr[3], rref[3];
+    int32_t state[3], stall[3], stall0[3], nres[3], restart[3];
     int32_t reason;
     int32_t nonfinite;
+    int32_t checked;
 };
 
 __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const SolveConst& sc,
-                                 const double (&red)[kKp], PScalars& o) {
+                                 const double (&red)[kKp], const double (&tr)[3], bool check, PScalars& o) {
     const int32_t j = it - 1;
     const int prev = j & 1;
     o.nonfinite = 0;
+    o.checked = check ? 1 : 0;
     int any_prog = 0;
     for (int c = 0; c < 3; ++c) {
         const double g = red[c];
@@ -85,9 +84,9 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
         } else {
             bb = ctl->bb[c];
             tau2 = ctl->tau2[c];
+            stall = ctl->stallB[prev][c];
             if (sc.variant == SPH_ROBUST) {
                 // alpha'_j = gamma_{j+1}/delta_j, beta_j = alpha'_j/omega_j
-                stall = ctl->stallB[prev][c];
                 if (!stall) {
                     ap = g / ctl->delta[prev][c];
                     if (!finite_d(ap)) ap = 0.0;
@@ -97,16 +96,19 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
                 if (g == 0.0) stall = 1;
             } else {
                 // beta_{j+1} = (gamma_{j+1}/gamma_j)(alpha_j/omega_j)
-                stall = ctl->stallB[prev][c];
                 const double gp = ctl->gam[prev][c], al = ctl->alpha[prev][c], om = ctl->omega[prev][c];
                 if (gp != 0.0 && om != 0.0) bt = (g / gp) * (al / om);
                 if (!finite_d(bt)) bt = 0.0;
             }
         }
+        int32_t nres = it == 1 ? 0 : ctl->nres[prev][c];
+        double rref = it == 1 ? rr : ctl->rr_ref[prev][c];
+        o.restart[c] = 0;
         if (it > 1 && ctl->restart_iter == j && ctl->restart[c]) {
-            // restarted from the true residual: fresh direction
+            // restarted by a host-issued check: fresh direction from r_true
             o.g[c] = ctl->gam_restart[c];
             o.rr[c] = ctl->rr_restart[c];
+            rref = ctl->rr_restart[c];
             o.ap[c] = 0.0;
             o.bt[c] = 0.0;
             o.state[c] = o.rr[c] < tau2 ? SPH_CONVERGED : SPH_PROGRESSING;
@@ -117,7 +119,34 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
             o.bt[c] = bt;
             o.state[c] = rr < tau2 ? SPH_CONVERGED : (stall ? SPH_STATE_STALLED : SPH_PROGRESSING);
         }
+        if (check) {
+            bool rs = false;
+            if (o.state[c] == SPH_CONVERGED && !(tr[c] < tau2)) {
+                // the recursion says converged, the true residual does not
+                if (nres < kMaxRestarts) {
+                    ++nres;
+                    rs = true;
+                } else {
+                    o.state[c] = SPH_STATE_STALLED;
+                }
+            } else if (o.state[c] == SPH_PROGRESSING && tr[c] < sc.drop * rref) {
+                rs = true;  // the residual has fallen far below the shadow vector
+            }
+            if (rs) {
+                // restart from the true residual (copied by the kernel body)
+                o.restart[c] = 1;
+                o.g[c] = tr[c];
+                o.rr[c] = tr[c];
+                o.ap[c] = 0.0;
+                o.bt[c] = 0.0;
+                o.state[c] = tr[c] < tau2 ? SPH_CONVERGED : SPH_PROGRESSING;
+                rref = tr[c];
+            }
+        }
         if (sc.variant == SPH_STANDARD && o.g[c] == 0.0) st0 = 1;  // breakdown of iteration it
+        o.trr[c] = tr[c];
+        o.nres[c] = nres;
+        o.rref[c] = rref;
         o.stall[c] = stall;
         o.stall0[c] = st0;
         o.tau2[c] = tau2;
@@ -126,25 +155,30 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
     }
     int32_t reason = 0;
     if (!any_prog || o.nonfinite) reason |= kHaltNoProg;
-    if (sc.true_res_period > 0 && j > 0 && j % sc.true_res_period == 0 && ctl->checked_iter != j)
-        reason |= kHaltPeriodic;
     if (j >= sc.max_iter) reason |= kHaltMaxIter;
     o.reason = reason;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
-                                                 const double* __restrict__ part, int32_t nblk, int64_t n,
-                                                 const T* __restrict__ r, T* __restrict__ p,
-                                                 const T* __restrict__ ap, double* __restrict__ hist,
-                                                 int32_t* __restrict__ stallhist) {
+__global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                    const double* __restrict__ part, int32_t nblk,
+                                                    const double* __restrict__ part_tr, int64_t n, T* __restrict__ r,
+                                                    T* __restrict__ rh0, T* __restrict__ p,
+                                                    const T* __restrict__ ap, const T* __restrict__ rt,
+                                                    double* __restrict__ hist, int32_t* __restrict__ stallhist) {
     if (ctl->halt) return;
-    __shared__ double lds[kKp * (kBlock / kWave)];
+    __shared__ double lds[kKp * kMaxWaves];
     double red[kKp];
     reduce_partials<kKp>(part, nblk, red, lds);
-    PScalars s;
-    p_scalars(ctl, it, sc, red, s);
     const int32_t j = it - 1;
+    // periodic FP64 true residual of iteration j, unless a host-issued check
+    // already covered it
+    const bool check = sc.true_res_period > 0 && j > 0 && j % sc.true_res_period == 0 &&
+                       ctl->host_checked_iter != j;
+    double tr[3] = {0.0, 0.0, 0.0};
+    if (check) reduce_partials<3>(part_tr, sc.tr_blocks, tr, lds);
+    PScalars s;
+    p_scalars(ctl, it, sc, red, tr, check, s);
     const int cur = it & 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
@@ -152,6 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t 
             ctl->alphap[cur][c] = s.ap[c];
             ctl->beta[cur][c] = s.bt[c];
             ctl->stall0[cur][c] = s.stall0[c];
+            ctl->nres[cur][c] = s.nres[c];
+            ctl->rr_ref[cur][c] = s.rref[c];
             ctl->rr[c] = s.rr[c];
             ctl->state[c] = s.state[c];
             if (it == 1) {
@@ -162,6 +198,14 @@ __global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t 
                 hist[3 * j + c] = s.rr[c];
                 stallhist[3 * j + c] = s.stall[c];
             }
+            if (s.checked) {
+                ctl->trr[c] = s.trr[c];
+                ctl->n_replaced += s.restart[c];
+            }
+        }
+        if (s.checked) {
+            ctl->n_true_checks += 1;
+            ctl->dev_checked_iter = j;
         }
         if (s.nonfinite) ctl->nonfinite = 1;
         ctl->halt_reason = s.reason;
@@ -172,13 +216,23 @@ __global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t 
     // body: p update; a zero coefficient skips its vector
     const bool use_p = s.bt[0] != 0.0 || s.bt[1] != 0.0 || s.bt[2] != 0.0;
     const bool use_ap = sc.variant == SPH_ROBUST ? (s.ap[0] != 0.0 || s.ap[1] != 0.0 || s.ap[2] != 0.0) : use_p;
+    const bool any_rs = s.restart[0] | s.restart[1] | s.restart[2];
     double om[3];
     for (int c = 0; c < 3; ++c) om[c] = sc.variant == SPH_ROBUST ? 0.0 : (it > 1 ? ctl->omega[j & 1][c] : 1.0);
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
-    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const V3<T> rv = ld3(r, i);
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        V3<T> rv = ld3(r, i);
+        if (any_rs) {
+            const V3<T> tv = ld3(rt, i);
+            V3<T> hv = ld3(rh0, i);
+            if (s.restart[0]) rv.x = hv.x = tv.x;
+            if (s.restart[1]) rv.y = hv.y = tv.y;
+            if (s.restart[2]) rv.z = hv.z = tv.z;
+            st3(r, i, rv);
+            st3(rh0, i, hv);
+        }
         V3<T> pv{}, av{};
         if (use_p) pv = ld3(p, i);
         if (use_ap) av = ld3(ap, i);
@@ -193,22 +247,18 @@ __global__ __launch_bounds__(kBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t 
                 o[c] = o[c] + (T)s.bt[c] * (pp[c] - (T)om[c] * aa[c]);
             }
         }
-        V3<T> out;
-        out.x = o[0];
-        out.y = o[1];
-        out.z = o[2];
-        st3(p, i, out);
+        st3(p, i, V3<T>{o[0], o[1], o[2]});
     }
 }
 
 // alpha_i = gamma_i/delta_i, then s = r - alpha A p.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_supd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
-                                                 const double* __restrict__ part, int32_t nblk, int64_t n,
-                                                 const T* __restrict__ r, const T* __restrict__ ap,
-                                                 T* __restrict__ s) {
+__global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                    const double* __restrict__ part, int32_t nblk, int64_t n,
+                                                    const T* __restrict__ r, const T* __restrict__ ap,
+                                                    T* __restrict__ s) {
     if (ctl->halt) return;
-    __shared__ double lds[3 * (kBlock / kWave)];
+    __shared__ double lds[3 * kMaxWaves];
     double red[3];
     reduce_partials<3>(part, nblk, red, lds);
     const int cur = it & 1;
@@ -236,30 +286,26 @@ __global__ __launch_bounds__(kBlock) void k_supd(Ctl* __restrict__ ctl, int32_t 
     }
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
-    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
     const T a0 = (T)al[0], a1 = (T)al[1], a2 = (T)al[2];
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const V3<T> rv = ld3(r, i);
         const V3<T> av = ld3(ap, i);
-        V3<T> o;
-        o.x = rv.x - a0 * av.x;
-        o.y = rv.y - a1 * av.y;
-        o.z = rv.z - a2 * av.z;
-        st3(s, i, o);
+        st3(s, i, V3<T>{rv.x - a0 * av.x, rv.y - a1 * av.y, rv.z - a2 * av.z});
     }
 }
 
 // omega_i = (s . A s)/(A s . A s); x = x + alpha p + omega s; r = s - omega A s;
 // partials of r0hat . r and r . r.
 template <typename T, int KA>
-__global__ __launch_bounds__(kBlock) void k_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
-                                                  const double* __restrict__ part, int32_t nblk, int64_t n,
-                                                  T* __restrict__ x, const T* __restrict__ p,
-                                                  const T* __restrict__ s, const T* __restrict__ as,
-                                                  T* __restrict__ r, const T* __restrict__ rh0,
-                                                  double* __restrict__ part_out) {
+__global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                     const double* __restrict__ part, int32_t nblk, int64_t n,
+                                                     T* __restrict__ x, const T* __restrict__ p,
+                                                     const T* __restrict__ s, const T* __restrict__ as,
+                                                     T* __restrict__ r, const T* __restrict__ rh0,
+                                                     double* __restrict__ part_out) {
     if (ctl->halt) return;
-    __shared__ double lds[kKp * (kBlock / kWave)];
+    __shared__ double lds[kKp * kMaxWaves];
     double red[KA];
     reduce_partials<KA>(part, nblk, red, lds);
     const int cur = it & 1;
@@ -290,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_close(Ctl* __restrict__ ctl, int32_t
     const T W[3] = {(T)om[0], (T)om[1], (T)om[2]};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
-    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const V3<T> xv = ld3(x, i), pv = ld3(p, i), sv = ld3(s, i), av = ld3(as, i), hv = ld3(rh0, i);
         const T xx[3] = {xv.x, xv.y, xv.z}, pp[3] = {pv.x, pv.y, pv.z}, ss[3] = {sv.x, sv.y, sv.z};
         const T aa[3] = {av.x, av.y, av.z}, hh[3] = {hv.x, hv.y, hv.z};
@@ -310,23 +356,24 @@ __global__ __launch_bounds__(kBlock) void k_close(Ctl* __restrict__ ctl, int32_t
     write_partials<kKp>(acc, lds, part_out);
 }
 
-// Residual check, step 2 (one block): decide which converged components
-// failed the FP64 true residual and must restart.
-__global__ __launch_bounds__(kBlock) void k_check_decide(Ctl* __restrict__ ctl, const double* __restrict__ part,
-                                                         int32_t nblk) {
-    __shared__ double lds[3 * (kBlock / kWave)];
+// Host-issued residual check, step 2 (one block): decide which converged
+// components failed the FP64 true residual and must restart.
+__global__ __launch_bounds__(kMaxBlock) void k_check_decide(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                            int32_t nblk) {
+    __shared__ double lds[3 * kMaxWaves];
     double red[3];
     reduce_partials<3>(part, nblk, red, lds);
     if (threadIdx.x != 0) return;
+    const int32_t j = ctl->iter;
     ctl->n_true_checks += 1;
     for (int c = 0; c < 3; ++c) {
         ctl->trr[c] = red[c];
         int rs = 0;
         if (ctl->state[c] == SPH_CONVERGED && !(red[c] < ctl->tau2[c])) {
-            if (ctl->n_restart[c] < kMaxRestarts) {
+            if (ctl->nres[j & 1][c] < kMaxRestarts) {
                 rs = 1;
                 ctl->state[c] = SPH_PROGRESSING;
-                ctl->n_restart[c] += 1;
+                ctl->nres[j & 1][c] += 1;
                 ctl->n_replaced += 1;
             } else {
                 ctl->state[c] = SPH_STATE_STALLED;
@@ -334,31 +381,31 @@ __global__ __launch_bounds__(kBlock) void k_check_decide(Ctl* __restrict__ ctl, 
         }
         ctl->restart[c] = rs;
     }
-    ctl->restart_iter = ctl->iter;
-    ctl->checked_iter = ctl->iter;
+    ctl->restart_iter = j;
+    ctl->host_checked_iter = j;
 }
 
-// Residual check, step 3: r = r0hat = r_true for restarted components, and
-// partials of the new r0hat . r, r . r.
+// Step 3: r = r0hat = r_true for restarted components, and partials of the
+// new r0hat . r, r . r.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_check_copy(const Ctl* __restrict__ ctl, int64_t n,
-                                                       const T* __restrict__ rt, T* __restrict__ r,
-                                                       T* __restrict__ rh0, double* __restrict__ part) {
-    __shared__ double lds[6 * (kBlock / kWave)];
+__global__ __launch_bounds__(kMaxBlock) void k_check_copy(const Ctl* __restrict__ ctl, int64_t n,
+                                                          const T* __restrict__ rt, T* __restrict__ r,
+                                                          T* __restrict__ rh0, double* __restrict__ part) {
+    __shared__ double lds[6 * kMaxWaves];
     double acc[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0.0;
     const int rs[3] = {ctl->restart[0], ctl->restart[1], ctl->restart[2]};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
-    const int64_t r0 = bid * rpb, r1 = min(r0 + rpb, n);
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
     if (rs[0] | rs[1] | rs[2]) {
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
             const V3<T> tv = ld3(rt, i);
             V3<T> rv = ld3(r, i), hv = ld3(rh0, i);
-            if (rs[0]) { rv.x = tv.x; hv.x = tv.x; }
-            if (rs[1]) { rv.y = tv.y; hv.y = tv.y; }
-            if (rs[2]) { rv.z = tv.z; hv.z = tv.z; }
+            if (rs[0]) rv.x = hv.x = tv.x;
+            if (rs[1]) rv.y = hv.y = tv.y;
+            if (rs[2]) rv.z = hv.z = tv.z;
             st3(r, i, rv);
             st3(rh0, i, hv);
             const double q[3] = {(double)rv.x, (double)rv.y, (double)rv.z};
@@ -371,9 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_check_copy(const Ctl* __restrict__ c
     write_partials<6>(acc, lds, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
-                                                         int32_t nblk) {
-    __shared__ double lds[6 * (kBlock / kWave)];
+__global__ __launch_bounds__(kMaxBlock) void k_check_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                            int32_t nblk) {
+    __shared__ double lds[6 * kMaxWaves];
     double red[6];
     reduce_partials<6>(part, nblk, red, lds);
     if (threadIdx.x != 0) return;
@@ -384,9 +431,9 @@ __global__ __launch_bounds__(kBlock) void k_check_finish(Ctl* __restrict__ ctl, 
 }
 
 // Final FP64 true residual, reduced into ctl->trr (one block).
-__global__ __launch_bounds__(kBlock) void k_final_trr(Ctl* __restrict__ ctl, const double* __restrict__ part,
-                                                      int32_t nblk) {
-    __shared__ double lds[3 * (kBlock / kWave)];
+__global__ __launch_bounds__(kMaxBlock) void k_final_trr(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                         int32_t nblk) {
+    __shared__ double lds[3 * kMaxWaves];
     double red[3];
     reduce_partials<3>(part, nblk, red, lds);
     if (threadIdx.x == 0)
@@ -398,7 +445,8 @@ __global__ void k_ctl_init(Ctl* ctl) {
     for (size_t i = threadIdx.x; i < sizeof(Ctl) / sizeof(int32_t); i += blockDim.x) w[i] = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        ctl->checked_iter = -1;
+        ctl->host_checked_iter = -1;
+        ctl->dev_checked_iter = -1;
         ctl->restart_iter = -1;
     }
 }
@@ -446,7 +494,7 @@ struct Solver {
     Launch L;
     T *b, *x, *r, *rh0, *p, *ap, *s, *as, *tmp;
     double* b64;
-    double *pa1, *pa2, *pk3, *pchk;
+    double *pa1, *pa2, *pk3, *ptr, *pchk;
     Ctl* ctl;
     double* hist;
     int32_t* stallhist;
@@ -471,25 +519,29 @@ struct Solver {
         return SPH_OK;
     }
 
+    dim3 ga() const { return dim3(L.grid_apply); }
+    dim3 ba() const { return dim3(L.block_apply); }
+    dim3 gs() const { return dim3(L.grid_stream); }
+    dim3 bs() const { return dim3(L.block_stream); }
+
     // y = A x fused with the dot products of mode MODE
     template <int MODE>
     void apply(const int32_t* halt, const T* xin, T* yout, const T* w, double* part) {
         if (mode == SPH_OP_CACHED)
-            hipLaunchKernelGGL((k_apply_sell<T, MODE>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream, halt,
-                               L.n, sell, xin, yout, w, part);
+            hipLaunchKernelGGL((k_apply_sell<T, MODE>), ga(), ba(), 0, ctx->stream, halt, L.n, sell, xin, yout, w,
+                               (const double*)b64, part);
         else
-            hipLaunchKernelGGL((k_apply_otf<T, MODE>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream, halt,
-                               nb->view(), pv, op, xin, yout, w, (const double*)nullptr, part);
+            hipLaunchKernelGGL((k_apply_otf<T, MODE>), ga(), ba(), 0, ctx->stream, halt, nb->view(), pv, op, xin,
+                               yout, w, (const double*)b64, part);
         ++launches;
     }
 
     sph_status iteration(int32_t it) {
         const int32_t* halt = &ctl->halt;
-        hipLaunchKernelGGL(k_pupd<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc, pk3,
-                           L.grid_stream, L.n, r, p, ap, hist, stallhist);
+        hipLaunchKernelGGL(k_pupd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
+                           (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist);
         apply<kDotA1>(halt, p, ap, rh0, pa1);
-        hipLaunchKernelGGL(k_supd<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc, pa1,
-                           L.grid_apply, L.n, r, ap, s);
+        hipLaunchKernelGGL(k_supd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pa1, L.grid_apply, L.n, r, ap, s);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (profile) {
             const int k = (int)recs.size();
@@ -501,32 +553,29 @@ struct Solver {
         if (sc.variant == SPH_STANDARD) {
             apply<kDotA2Std>(halt, s, as, nullptr, pa2);
             if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 9>), dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc,
-                               pa2, L.grid_apply, L.n, x, p, s, as, r, rh0, pk3);
+            hipLaunchKernelGGL((k_close<T, 9>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
+                               p, s, as, r, rh0, pk3);
         } else {
             apply<kDotA2>(halt, s, as, nullptr, pa2);
             if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 6>), dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, it, sc,
-                               pa2, L.grid_apply, L.n, x, p, s, as, r, rh0, pk3);
+            hipLaunchKernelGGL((k_close<T, 6>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
+                               p, s, as, r, rh0, pk3);
         }
         launches += 3;
+        // the next p update applies the periodic FP64 residual check
+        if (sc.true_res_period > 0 && it % sc.true_res_period == 0) true_residual(halt, ptr);
         return SPH_OK;
     }
 
-    // FP64 true residual of the current x into tmp, partials into pchk.
-    void true_residual() {
-        hipLaunchKernelGGL((k_apply_otf<T, kDotResid>), dim3(L.grid_apply), dim3(kBlock), 0, ctx->stream,
-                           (const int32_t*)nullptr, nb->view(), pv, op, x, tmp, (const T*)nullptr,
-                           (const double*)b64, pchk);
-        ++launches;
-    }
+    // FP64-accurate b - A x of the current x into tmp, partials into `part`.
+    void true_residual(const int32_t* halt, double* part) { apply<kDotResid>(halt, x, tmp, nullptr, part); }
 
-    void check() {
-        true_residual();
-        hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kBlock), 0, ctx->stream, ctl, pchk, L.grid_apply);
-        hipLaunchKernelGGL(k_check_copy<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, ctl, L.n, tmp, r,
-                           rh0, pchk + 3 * (size_t)L.grid_apply);
-        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctl,
+    void host_check() {
+        true_residual(nullptr, pchk);
+        hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl, pchk, L.grid_apply);
+        hipLaunchKernelGGL(k_check_copy<T>, gs(), bs(), 0, ctx->stream, ctl, L.n, tmp, r, rh0,
+                           pchk + 3 * (size_t)L.grid_apply);
+        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl,
                            pchk + 3 * (size_t)L.grid_apply, L.grid_stream);
         launches += 3;
     }
@@ -571,13 +620,18 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     SPH_TRY(ctx->ensure_t(kPartA1, (size_t)L.grid_apply * 3, &S.pa1));
     SPH_TRY(ctx->ensure_t(kPartA2, (size_t)L.grid_apply * 9, &S.pa2));
     SPH_TRY(ctx->ensure_t(kPartK3, (size_t)L.grid_stream * kKp, &S.pk3));
-    SPH_TRY(ctx->ensure_t(kPartChk, (size_t)L.grid_apply * 3 + (size_t)L.grid_stream * 6, &S.pchk));
+    // [host check: residual (3 per apply block), copy (6 per stream block) |
+    //  periodic device check: residual (3 per apply block)]
+    SPH_TRY(ctx->ensure_t(kPartChk, (size_t)L.grid_apply * 6 + (size_t)L.grid_stream * 6, &S.pchk));
+    S.ptr = S.pchk + 3 * (size_t)L.grid_apply + 6 * (size_t)L.grid_stream;
     SPH_TRY(ctx->ensure_t(kCtl, 1, &S.ctl));
     const int32_t hist_rows = o->max_iter + 1;
     SPH_TRY(ctx->ensure_t(kHist, (size_t)hist_rows * 3, &S.hist));
     SPH_TRY(ctx->ensure_t(kStallHist, (size_t)hist_rows * 3, &S.stallhist));
 
     S.sc.tol2 = o->tol * o->tol;
+    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : (prec == SPH_F32 ? 1e-6 : 0.0);
+    S.sc.tr_blocks = L.grid_apply;
     S.sc.floor_ = o->floor >= 0.0 ? o->floor : (prec == SPH_F32 ? (double)FLT_MIN : DBL_MIN);
     S.sc.max_iter = o->max_iter;
     S.sc.variant = o->variant;
@@ -593,17 +647,17 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     S.launches += 2;
     SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
     SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
-    const T* ax = nullptr;
+    const T* r0 = nullptr;
     if (o->x0_given) {
+        // r0 = b - A x0 with the FP64-accurate operator
         SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
-        S.template apply<kDotNone>(nullptr, S.x, S.tmp, nullptr, nullptr);
-        ax = S.tmp;
+        S.true_residual(nullptr, S.pchk);
+        r0 = S.tmp;
         ++S.launches;
     } else {
         SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
     }
-    hipLaunchKernelGGL(k_init<T>, dim3(L.grid_stream), dim3(kBlock), 0, ctx->stream, n, S.b, ax, S.r, S.rh0,
-                       S.pk3);
+    hipLaunchKernelGGL(k_init<T>, S.gs(), S.bs(), 0, ctx->stream, n, S.b, r0, S.r, S.rh0, S.pk3);
     ++S.launches;
     SPH_LAUNCHED("solve setup");
     SPH_HIP(hipEventRecord(e1, ctx->stream));
@@ -614,7 +668,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         int32_t halt, reason;  // Ctl::halt and Ctl::halt_reason, adjacent
     };
     Mail* mail = static_cast<Mail*>(ctx->host_mail);
-    const int kmax = o->poll_every > 0 ? o->poll_every : 16;
+    const int kmax = o->poll_every > 0 ? o->poll_every : 8;
     const int32_t last_it = o->max_iter + 1;  // P of this iteration always halts
     int32_t j = 0;
     Ctl hctl;
@@ -645,17 +699,15 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
                 halted = true;
             }
         }
-        SPH_HIP(hipStreamSynchronize(ctx->stream));
         SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
         if (hctl.nonfinite) return ctx->fail(SPH_E_NONFINITE, "visc_solve: non-finite right-hand side");
         if (!hctl.halt) return ctx->fail(SPH_E_HIP, "visc_solve: iteration issue ended without a halt");
         j = hctl.iter;
         S.round_end.push_back(j);
         ++S.round;
-        if (hctl.halt_reason & (kHaltNoProg | kHaltPeriodic)) {
-            S.check();
+        if ((hctl.halt_reason & kHaltNoProg) && hctl.dev_checked_iter != j && hctl.host_checked_iter != j) {
+            S.host_check();
             SPH_LAUNCHED("residual check");
-            SPH_HIP(hipStreamSynchronize(ctx->stream));
             SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
         }
         bool any_prog = false;
@@ -663,15 +715,16 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         if (!any_prog || j >= o->max_iter) break;
         SPH_HIP(hipMemsetAsync(&S.ctl->halt, 0, sizeof(int32_t), ctx->stream));
     }
-    // final FP64 true residual for the report
-    S.true_residual();
-    hipLaunchKernelGGL(k_final_trr, dim3(1), dim3(kBlock), 0, ctx->stream, S.ctl, S.pchk, L.grid_apply);
-    ++S.launches;
+    // FP64 true residual of the final x for the report, unless the last check covered it
+    if (hctl.dev_checked_iter != j && hctl.host_checked_iter != j) {
+        S.true_residual(nullptr, S.pchk);
+        hipLaunchKernelGGL(k_final_trr, dim3(1), dim3(kMaxBlock), 0, ctx->stream, S.ctl, S.pchk, L.grid_apply);
+        S.launches += 1;
+    }
     SPH_TRY(scatter_vec3<T>(ctx, nb, S.x, xout));
     ++S.launches;
     SPH_LAUNCHED("solve finish");
     SPH_HIP(hipEventRecord(e2, ctx->stream));
-    SPH_HIP(hipStreamSynchronize(ctx->stream));
     SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
 
     rep->iters = hctl.iter;
@@ -699,7 +752,8 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     rep->history_len = 0;
     if (rep->history && rep->history_cap > 0) {
         const int32_t hl = std::min(rows, rep->history_cap);
-        SPH_HIP(hipMemcpyAsync(rep->history, S.hist, sizeof(double) * (size_t)hl * 3, hipMemcpyDeviceToHost, ctx->stream));
+        SPH_HIP(hipMemcpyAsync(rep->history, S.hist, sizeof(double) * (size_t)hl * 3, hipMemcpyDeviceToHost,
+                               ctx->stream));
         SPH_HIP(hipStreamSynchronize(ctx->stream));
         rep->history_len = hl;
     }
@@ -712,10 +766,10 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     if (S.profile) {
         double tot = 0.0;
         int32_t cnt = 0;
-        for (const auto& r : S.recs) {
-            if (r.round >= (int32_t)S.round_end.size() || r.it > S.round_end[r.round]) continue;  // returned at once
+        for (const auto& rc : S.recs) {
+            if (rc.round >= (int32_t)S.round_end.size() || rc.it > S.round_end[rc.round]) continue;  // returned at once
             float ms = 0.f;
-            SPH_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * r.ev], ctx->prof_ev[2 * r.ev + 1]));
+            SPH_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * rc.ev], ctx->prof_ev[2 * rc.ev + 1]));
             tot += ms;
             ++cnt;
         }

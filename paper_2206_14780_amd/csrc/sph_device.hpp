@@ -164,7 +164,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Block-wide sum of K values per thread; result valid in every thread.
-// `lds` must hold K * (blockDim.x / 64) doubles.
+// `lds` must hold K * kMaxWaves doubles.
 template <int K>
 __device__ inline void block_sum(double (&v)[K], double* lds) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -175,13 +175,13 @@ __device__ inline void block_sum(double (&v)[K], double* lds) {
     __syncthreads();
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) lds[k * nw + wid] = v[k];
+        for (int k = 0; k < K; ++k) lds[k * kMaxWaves + wid] = v[k];
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += lds[k * nw + w];
+        for (int w = 0; w < nw; ++w) s += lds[k * kMaxWaves + w];
         v[k] = s;
     }
     __syncthreads();

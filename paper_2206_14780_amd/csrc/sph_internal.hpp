@@ -13,7 +13,9 @@
 namespace sph {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kBlock = 256;        // threads per block of the row kernels (4 waves)
+constexpr int kBlock = 256;        // threads per block of the simple per-particle kernels
+constexpr int kMaxBlock = 1024;    // largest block of the row kernels
+constexpr int kMaxWaves = kMaxBlock / kWave;
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
 constexpr double kPi = 3.14159265358979323846;
 
@@ -58,15 +60,26 @@ struct OpParams {
 };
 
 // Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).
-// Entry k of row r = s*64 + l lives at sl_ptr[s] + k*64 + l; rows shorter
-// than their slice are padded with (col = r, coef = 0).
+// Entry k of row r = s*64 + l lives at slot sl_ptr[s] + k*64 + l; rows
+// shorter than their slice are padded with (col = r, coef = 0).  The operator
+// is applied in difference form, y_r = rs_r x_r + sum_k coef[r,k] (x_col - x_r),
+// with rs_r the row sum of the matrix, which the structure of A fixes exactly
+// (1/A_rr for a Jacobi-scaled fluid row, 1 unscaled, 2 for a dummy-wall row
+// with fluid neighbours, 1 for identity rows).
+//   FP32: pk[slot] = (col, bits of the coefficient rounded to FP32) and
+//         lo[slot] = coefficient - (double)hi, so hi + lo carries ~48 bits
+//         for the FP64-accurate residual;
+//   FP64: cols[slot], coef[slot].
 template <typename T>
 struct Sell {
     int64_t nslices;
     const int64_t* sl_ptr;  // [nslices + 1]
-    const int32_t* cols;
-    const T* coef;
-    const T* dg;            // diagonal of the (scaled) matrix, per row
+    const int2* pk;         // FP32 only
+    const float* lo;        // FP32 only
+    const int32_t* cols;    // FP64 only
+    const T* coef;          // FP64 only
+    const T* dg;            // row sum of the (scaled) matrix, per row
+    const double* rs64;     // the same row sums in FP64
 };
 
 // ---------------------------------------------------------------------------
@@ -87,6 +100,8 @@ struct Ctl {
     double alphap[2][3];  // alpha'_{i-1}
     double beta[2][3];    // beta_{i-1}
     int32_t stall0[2][3]; // textbook variant: gamma_i == 0
+    int32_t nres[2][3];   // failed-check restarts so far (slot it&1 written by iteration it)
+    double rr_ref[2][3];  // true r.r at the last (re)start
     double rr[3];         // r.r of the last completed iteration
     double bb[3];
     double tau2[3];
@@ -94,6 +109,7 @@ struct Ctl {
     int32_t iter;         // iterations started
     int32_t halt;         // nonzero: every iteration kernel returns at once
     int32_t halt_reason;
+    int32_t dev_checked_iter;  // last iteration checked by the p-update kernel
     // written by the s-update kernel (block 0)
     double delta[2][3];
     double alpha[2][3];
@@ -101,14 +117,13 @@ struct Ctl {
     // written by the close-out kernel (block 0)
     double omega[2][3];
     int32_t stallB[2][3];
-    // written by the residual-check kernels
+    // written by the residual-check kernels (p-update block 0 or host-issued)
     double trr[3];
     double gam_restart[3];
     double rr_restart[3];
     int32_t restart[3];
-    int32_t n_restart[3];
     int32_t restart_iter;
-    int32_t checked_iter;
+    int32_t host_checked_iter;  // last iteration checked by host-issued kernels
     int32_t n_true_checks;
     int32_t n_replaced;
     int32_t nonfinite;
@@ -117,6 +132,8 @@ struct Ctl {
 // Constants of one solve, passed by value to the iteration kernels.
 struct SolveConst {
     double tol2;
+    double drop;           // restart when r_true.r_true < drop * rr_ref (0 = never)
+    int32_t tr_blocks;     // blocks (partials) of the true-residual kernel
     double floor_;
     int32_t max_iter;
     int32_t variant;
@@ -130,7 +147,9 @@ struct SolveConst {
 struct Launch {
     int64_t n;
     int32_t grid_apply;    // blocks of the operator kernels
+    int32_t block_apply;   // threads per operator block (multiple of 64, <= kMaxBlock)
     int32_t grid_stream;   // blocks of the streaming kernels
+    int32_t block_stream;  // threads per streaming block
 };
 
 Launch make_launch(int64_t n);
@@ -139,7 +158,7 @@ Launch make_launch(int64_t n);
 // Device workspace: named, monotonically growing allocations of a context.
 // ---------------------------------------------------------------------------
 enum Slot : int {
-    kMass, kRho, kMu, kType, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg,
+    kMass, kRho, kMu, kType, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg, kPk, kLo, kRs64,
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kNumSlots

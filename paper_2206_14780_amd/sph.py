@@ -48,7 +48,8 @@ class sph_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("variant", C.c_int32),
                 ("floor", C.c_double), ("true_res_period", C.c_int32), ("x0_given", C.c_int32),
                 ("poll_every", C.c_int32), ("force_stall_iter", C.c_int32),
-                ("force_stall_comp", C.c_int32), ("profile", C.c_int32)]
+                ("force_stall_comp", C.c_int32), ("profile", C.c_int32),
+                ("restart_drop", C.c_double)]
 
 
 class sph_solve_report(C.Structure):
@@ -155,11 +156,12 @@ def make_params(dt, wall, avg, jacobi=True, op_mode=SPH_OP_CACHED) -> sph_visc_p
 
 
 def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res_period=50,
-              x0_given=False, poll_every=0, force_stall=None, profile=False) -> sph_solve_opts:
+              x0_given=False, poll_every=0, force_stall=None, profile=False,
+              restart_drop=-1.0) -> sph_solve_opts:
     fi, fc = force_stall if force_stall is not None else (-1, -1)
     return sph_solve_opts(float(tol), int(max_iter), int(variant), float(floor),
                           int(true_res_period), int(bool(x0_given)), int(poll_every), int(fi), int(fc),
-                          int(bool(profile)))
+                          int(bool(profile)), float(restart_drop))
 
 
 class Context:

@@ -222,3 +222,16 @@ def test_deterministic(ctx):
     a, ra = g.solve(w.rhs, S.SPH_F32, tol=1e-6)
     b, rb = g.solve(w.rhs, S.SPH_F32, tol=1e-6)
     assert np.array_equal(a, b) and ra["history"] == rb["history"]
+
+
+def test_restart_on_drop_matches_oracle_fp64(ctx):
+    # The FP32 path's restart rule, exercised in FP64 so that GPU and oracle
+    # take the same decisions: same restart count, same solution.
+    w = small_tank(seed=81, dt_nu=30.0)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-12, true_res_period=5, restart_drop=1e-4)
+    Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-12, true_res_period=5, restart_drop=1e-4)
+    assert rep["status"] == 0 and ro["n_replaced"] >= 3
+    assert rep["n_replaced"] == ro["n_replaced"] and rep["n_true_checks"] == ro["n_true_checks"]
+    assert abs(rep["iters"] - ro["iters"]) <= 1
+    assert rel_l2(X, Xo) < 1e-10

@@ -52,7 +52,8 @@ STRUCTS = {
     "sph_domain": ["lo", "hi", "periodic", "h"],
     "sph_visc_params": ["dt", "wall", "avg", "jacobi", "op_mode"],
     "sph_solve_opts": ["tol", "max_iter", "variant", "floor", "true_res_period", "x0_given",
-                       "poll_every", "force_stall_iter", "force_stall_comp", "profile"],
+                       "poll_every", "force_stall_iter", "force_stall_comp", "profile",
+                       "restart_drop"],
     "sph_solve_report": ["iters", "status", "state", "stall_count", "rr", "bb", "tau2", "true_rr",
                          "n_true_checks", "n_replaced", "history", "history_cap", "history_len",
                          "setup_ms", "iterate_ms", "launches", "mat_nnz", "mat_slots", "apply_ms",

@@ -174,3 +174,16 @@ def test_true_residual_agrees_with_recursive_in_fp64():
     for c in range(3):
         assert rep["true_rr"][c] < rep["tau2"][c]
         assert abs(np.sqrt(rep["true_rr"][c]) - np.sqrt(rep["rr"][c])) < 1e-3 * np.sqrt(rep["tau2"][c])
+
+
+def test_restart_on_drop_still_reaches_the_direct_answer():
+    # Restarting from the true residual whenever it has fallen 1e4 below its
+    # value at the last restart changes the iterates, not the answer.
+    kw, pt = _tank(wall=W.WALL_DUMMY, mu_span=100.0, dt_nu=30.0)
+    op = O.Operator(jacobi=True, **kw)
+    B = np.random.default_rng(12).normal(size=(pt.size, 3))
+    X, rep, _ = O.solve(op, B, tol=1e-13, true_res_period=5, restart_drop=1e-4)
+    X0, rep0, _ = O.solve(op, B, tol=1e-13, true_res_period=5)
+    assert rep["status"] == 0 and rep["n_replaced"] >= 3 and rep0["n_replaced"] == 0
+    Xd = O.dense_solve(op, B)
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 1e-10
