@@ -25,6 +25,26 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-6 residual per solve, particle-iters/s, HBM GB/s; plain vs learned"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_apply_sell_f32_A2_open_box100_hbm.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in txt.splitlines()
+                  if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "source_files:")))
+    h = hashlib.sha256()
+    for f in fields.get("source_files", "").split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != fields.get("source_sha256", "").strip():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -37,6 +57,9 @@ def parse():
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-sample-iters", type=int, default=4,
                     help="BiCGSTAB iterations of the oracle's timed sample (0 = skip)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB on the device once "
+                         "(a kernel of known traffic to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -100,6 +123,12 @@ def main():
         return rep
 
     print(f"[bench] workload open_box{args.n} n={w.n} prec={args.prec} op={args.op_mode}", flush=True)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -127,8 +156,9 @@ def main():
     roofline = None
     if op_mode == S.SPH_OP_CACHED and a_ms > 0:
         achieved = alg_bytes / (a_ms * 1e-3) / 1e9
+        traffic = measured_traffic() if (args.n == 100 and prec == S.SPH_F32) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": f"k_apply_sell<{'float' if esz == 4 else 'double'}, kDotA2>",
                     "avg_launch_ms": round(a_ms, 4), "alg_bytes_per_launch": int(alg_bytes),
                     "mat_nnz": int(nnz), "mat_slots": int(slots)}
