@@ -24,5 +24,5 @@ def gpu_available() -> bool:
 @pytest.fixture(scope="session")
 def sph():
     """The HIP library binding; on a GPU machine a missing library is an error."""
-    from paper_2206_14780_amd import _lib
-    return _lib.load()
+    from paper_2206_14780_amd import sph as binding
+    return binding.load()
