@@ -119,7 +119,14 @@ typedef struct {
  *          r.r at the last (re)start restarts from the true residual
  *          (r0hat = r = r_true, alpha' = beta = 0).  Keeps the shadow vector
  *          commensurate with the residual when vectors are FP32.  < 0 selects
- *          1e-6 (SPH_F32) or 0 = never (SPH_F64). */
+ *          1e-6 (SPH_F32) or 0 = never (SPH_F64).
+ *   warm_params: device, SPH_MLP_NPARAM floats, or null.  Non-null: the
+ *          solve also forms the learned initial guess of sph_mlp_warmstart
+ *          (features from warm_u, or from rhs where warm_u[c] is null) and,
+ *          per component, starts from whichever of the learned guess and the
+ *          plain start (x on entry if x0_given, else zero) has the smaller
+ *          FP64 true residual.  The tolerance and stopping test are unchanged.
+ *   warm_u: device, n values of the precision each (the current velocity u). */
 typedef struct {
     double tol;
     int32_t max_iter;
@@ -132,6 +139,8 @@ typedef struct {
     int32_t force_stall_comp;
     int32_t profile;
     double restart_drop;
+    const float *warm_params;
+    const void *warm_u[3];
 } sph_solve_opts;
 
 /* Solve report (host memory).  history, if non-null, is a host buffer of
@@ -158,6 +167,12 @@ typedef struct {
     int64_t mat_slots;      /* stored entries including slice padding (SPH_OP_CACHED) */
     double apply_ms;        /* with opts->profile: summed duration of the timed launches */
     int32_t apply_launches; /* with opts->profile: number of timed launches */
+    /* learned initial guess (opts->warm_params non-null) */
+    int32_t warm_used[3];   /* 1: the component started from the learned guess */
+    double warm_rr[3];      /* true r.r of the learned guess (scaled system) */
+    double plain_rr[3];     /* true r.r of the plain start */
+    double warm_scale;      /* U, the normalisation of the features */
+    double warm_ms;         /* device time of forming the learned guess and both residuals */
 } sph_solve_report;
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
@@ -206,6 +221,60 @@ sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom
                           const sph_particles *p, const sph_visc_params *params, int32_t prec,
                           const void *const rhs[3], void *const x[3], const sph_solve_opts *opts,
                           sph_solve_report *report);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess.  Not part of the paper, which names better initial
+ * guesses as future work (Sections "Conclusions and future work" and
+ * "Implementation notes"): a per-particle MLP
+ *   x[4] -> 64 -> 64 -> 64 -> o[3] (ReLU), pred = o . B,
+ * one sample per fluid particle and velocity component, with
+ *   features x = (u_c / U, (u - A u)_c / U, log10 nu, log10(dt nu / h^2)),
+ *   basis    B = (b_c / U, u_c / U, (u - A u)_c / U),  target t = V_c / U,
+ * A the unscaled matrix of sph_visc_params, u the current velocity, b the
+ * right-hand side, nu = mu / rho, U the RMS of b over fluid rows and
+ * components.  The initial guess is x0_c = U pred on fluid rows; wall rows
+ * take b (dynamic model) or satisfy their own row exactly, x0_w = b_w -
+ * sum_a W x0_a / sum_a W (dummy model).
+ * Parameters: one FP32 vector of SPH_MLP_NPARAM values (W1 [4][64], b1,
+ * W2 [64][64], b2, W3 [64][64], b3, W4 [64][3], b4; matrices [in][out]).
+ * The weights enter every product as BF16; accumulation is FP32.
+ * ------------------------------------------------------------------------ */
+#define SPH_MLP_NPARAM 8835
+#define SPH_MLP_SAMPLE 8 /* floats per sample: x[4], B[3], t */
+
+/* Samples of one configuration, for training: samples (device, FP32,
+ * 3 n x SPH_MLP_SAMPLE) receives sample 3 k + c for particle k (original
+ * order) and component c; wall particles get all-zero samples.  u[c],
+ * rhs[c], target[c]: device, n doubles each (target may be null: t = 0).
+ * *U (host) receives the normalisation.  A u is evaluated in FP64. */
+sph_status sph_mlp_samples(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
+                           const sph_visc_params *params, const double *const u[3],
+                           const double *const rhs[3], const double *const target[3],
+                           float *samples, double *U);
+/* The learned initial guess alone (no fallback): x0[c] (device, n values of
+ * the precision, original order) = U (o . B) on fluid rows, rhs on dynamic
+ * wall rows, and on dummy wall rows the value that satisfies the row
+ * exactly.  u[c], rhs[c]: device, n values of the precision each;
+ * mlp_params: device, SPH_MLP_NPARAM floats.  *U (host, may be null)
+ * receives the normalisation. */
+sph_status sph_mlp_warmstart(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
+                             const sph_visc_params *params, int32_t prec, const void *const u[3],
+                             const void *const rhs[3], const float *mlp_params, void *const x0[3],
+                             double *U);
+/* out (device, n x 4) = (o0, o1, o2, pred) of samples (device, n x SPH_MLP_SAMPLE). */
+sph_status sph_mlp_forward(sph_ctx *ctx, const float *samples, int64_t n, const float *params,
+                           float *out);
+/* Gradient (device, SPH_MLP_NPARAM) of the mean squared error of the batch
+ * samples[idx[0 .. batch)] (idx: device int32); *loss (host) = that error. */
+sph_status sph_mlp_grad(sph_ctx *ctx, const float *samples, const int32_t *idx, int64_t batch,
+                        const float *params, float *grad, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on the FP32 master parameters (device) with moment buffers adam_m, adam_v
+ * (device, SPH_MLP_NPARAM each, zero before step 1); *loss (host, may be
+ * null) = mean squared error of the batch before the step. */
+sph_status sph_mlp_train_step(sph_ctx *ctx, const float *samples, const int32_t *idx,
+                              int64_t batch, float *params, float *adam_m, float *adam_v,
+                              int32_t step, double lr, double *loss);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cfloat>
 
+#include "mlp.hpp"
 #include "operator_kernels.hpp"
 
 namespace sph {
@@ -645,10 +646,34 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
                        nb->perm, (const T*)rhs[0], (const T*)rhs[1], (const T*)rhs[2], S.diag64, S.op.jacobi,
                        S.b64, S.b);
     S.launches += 2;
-    SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
-    SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
     const T* r0 = nullptr;
-    if (o->x0_given) {
+    double* winfo = nullptr;
+    if (o->warm_params) {
+        // learned start (x_l in s, its residual in as) against the plain
+        // start (x, its residual in tmp), per component by true r.r
+        SPH_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+        SPH_TRY(ctx->ensure_t(kWarmInfo, kWiSize, &winfo));
+        const void* uu[3];
+        for (int c = 0; c < 3; ++c) uu[c] = o->warm_u[c] ? o->warm_u[c] : rhs[c];
+        SPH_TRY(gather_vec3<T>(ctx, nb, uu, S.p));
+        const WarmOp<T> w{nb, S.pv, S.op, S.mode, &S.sell, S.diag64};
+        SPH_TRY(warm_learned<T>(ctx, w, rhs, S.p, o->warm_params, S.s, winfo));
+        double* pl = S.pchk;
+        double* pp = S.pchk + 3 * (size_t)L.grid_apply;
+        S.template apply<kDotResid>(nullptr, S.s, S.as, nullptr, pl);
+        if (o->x0_given) {
+            SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
+            S.template apply<kDotResid>(nullptr, S.x, S.tmp, nullptr, pp);
+        } else {
+            SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
+            SPH_TRY(warm_zero_rr(ctx, n, L.grid_apply, S.b64, pp));
+        }
+        SPH_TRY(warm_select<T>(ctx, n, L.grid_stream, L.block_stream, pl, pp, L.grid_apply, o->x0_given, S.x,
+                               S.s, S.as, S.b, S.tmp, winfo));
+        r0 = S.tmp;
+        S.launches += 11;
+        SPH_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
+    } else if (o->x0_given) {
         // r0 = b - A x0 with the FP64-accurate operator
         SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
         S.true_residual(nullptr, S.pchk);
@@ -657,6 +682,8 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     } else {
         SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
     }
+    SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
+    SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
     hipLaunchKernelGGL(k_init<T>, S.gs(), S.bs(), 0, ctx->stream, n, S.b, r0, S.r, S.rh0, S.pk3);
     ++S.launches;
     SPH_LAUNCHED("solve setup");
@@ -775,6 +802,20 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         }
         rep->apply_ms = tot;
         rep->apply_launches = cnt;
+    }
+    if (winfo) {
+        double wi[kWiSize];
+        SPH_HIP(hipMemcpyAsync(wi, winfo, sizeof(wi), hipMemcpyDeviceToHost, ctx->stream));
+        SPH_HIP(hipStreamSynchronize(ctx->stream));
+        for (int c = 0; c < 3; ++c) {
+            rep->warm_used[c] = wi[kWiUse + c] != 0.0;
+            rep->warm_rr[c] = wi[kWiRrL + c];
+            rep->plain_rr[c] = wi[kWiRrP + c];
+        }
+        rep->warm_scale = wi[kWiU];
+        float ms = 0.f;
+        SPH_HIP(hipEventElapsedTime(&ms, ctx->ev[5], ctx->ev[6]));
+        rep->warm_ms = ms;
     }
     rep->status = any_prog ? SPH_NOT_CONVERGED : (any_stall ? SPH_STALLED : SPH_OK);
     return (sph_status)rep->status;

@@ -161,7 +161,8 @@ enum Slot : int {
     kMass, kRho, kMu, kType, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg, kPk, kLo, kRs64,
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
-    kApplyIn, kApplyOut, kExportCnt, kNnzCount, kNumSlots
+    kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,
+    kNumSlots
 };
 
 }  // namespace sph
@@ -173,7 +174,7 @@ struct sph_ctx {
     void* ws[sph::kNumSlots] = {};
     size_t ws_bytes[sph::kNumSlots] = {};
     void* host_mail = nullptr;   // pinned host mailbox for polling the control block
-    hipEvent_t ev[5] = {};        // 0-2: solve timing, 3-4: halt polls
+    hipEvent_t ev[7] = {};        // 0-2: solve timing, 3-4: halt polls, 5-6: learned start
     std::vector<hipEvent_t> prof_ev;  // pairs bracketing profiled launches
 
     sph_status fail(sph_status s, const std::string& what);

@@ -25,6 +25,7 @@ SPH_AVG_ARITH, SPH_AVG_HARMONIC = 0, 1
 SPH_ROBUST, SPH_STANDARD = 0, 1
 SPH_OP_CACHED, SPH_OP_ONTHEFLY = 0, 1
 SPH_CONVERGED, SPH_STATE_STALLED, SPH_PROGRESSING = 0, 1, 2
+SPH_MLP_NPARAM, SPH_MLP_SAMPLE = 8835, 8
 
 _vp = C.c_void_p
 
@@ -49,7 +50,7 @@ class sph_solve_opts(C.Structure):
                 ("floor", C.c_double), ("true_res_period", C.c_int32), ("x0_given", C.c_int32),
                 ("poll_every", C.c_int32), ("force_stall_iter", C.c_int32),
                 ("force_stall_comp", C.c_int32), ("profile", C.c_int32),
-                ("restart_drop", C.c_double)]
+                ("restart_drop", C.c_double), ("warm_params", _vp), ("warm_u", _vp * 3)]
 
 
 class sph_solve_report(C.Structure):
@@ -60,7 +61,9 @@ class sph_solve_report(C.Structure):
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
                 ("history_len", C.c_int32), ("setup_ms", C.c_double), ("iterate_ms", C.c_double),
                 ("launches", C.c_int32), ("mat_nnz", C.c_int64), ("mat_slots", C.c_int64),
-                ("apply_ms", C.c_double), ("apply_launches", C.c_int32)]
+                ("apply_ms", C.c_double), ("apply_launches", C.c_int32),
+                ("warm_used", C.c_int32 * 3), ("warm_rr", C.c_double * 3),
+                ("plain_rr", C.c_double * 3), ("warm_scale", C.c_double), ("warm_ms", C.c_double)]
 
 
 _lib = None
@@ -79,6 +82,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    # torch first: the library must bind to the HIP runtime torch has loaded,
+    # not bring in a second copy that does not know torch's device state
+    import torch  # noqa: F401
     L = C.CDLL(path)
     i32, i64, st = C.c_int32, C.c_int64, C.c_int
     P = C.POINTER
@@ -96,9 +102,18 @@ def load(path: str = LIB_PATH):
     L.sph_visc_apply.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp), P(_vp)]
     L.sph_visc_solve.argtypes = [_vp, _vp, P(sph_domain), P(sph_particles), P(sph_visc_params), i32,
                                  P(_vp), P(_vp), P(sph_solve_opts), P(sph_solve_report)]
+    L.sph_mlp_samples.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), P(_vp), P(_vp),
+                                  P(_vp), _vp, P(C.c_double)]
+    L.sph_mlp_warmstart.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp),
+                                    P(_vp), _vp, P(_vp), P(C.c_double)]
+    L.sph_mlp_forward.argtypes = [_vp, _vp, i64, _vp, _vp]
+    L.sph_mlp_grad.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, P(C.c_double)]
+    L.sph_mlp_train_step.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, _vp, i32, C.c_double,
+                                     P(C.c_double)]
     for f in ("sph_create", "sph_destroy", "sph_set_stream", "sph_build_neighbors",
               "sph_neighbors_info", "sph_neighbors_export", "sph_neighbors_free", "sph_visc_apply",
-              "sph_visc_solve"):
+              "sph_visc_solve", "sph_mlp_samples", "sph_mlp_warmstart", "sph_mlp_forward",
+              "sph_mlp_grad", "sph_mlp_train_step"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -157,17 +172,28 @@ def make_params(dt, wall, avg, jacobi=True, op_mode=SPH_OP_CACHED) -> sph_visc_p
 
 def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res_period=50,
               x0_given=False, poll_every=0, force_stall=None, profile=False,
-              restart_drop=-1.0) -> sph_solve_opts:
+              restart_drop=-1.0, warm_params=None, warm_u=None) -> sph_solve_opts:
+    """Solver options; warm_params / warm_u are cuda tensors (kept alive by
+    the caller for the duration of the solve)."""
     fi, fc = force_stall if force_stall is not None else (-1, -1)
-    return sph_solve_opts(float(tol), int(max_iter), int(variant), float(floor),
-                          int(true_res_period), int(bool(x0_given)), int(poll_every), int(fi), int(fc),
-                          int(bool(profile)), float(restart_drop))
+    o = sph_solve_opts(float(tol), int(max_iter), int(variant), float(floor),
+                       int(true_res_period), int(bool(x0_given)), int(poll_every), int(fi), int(fc),
+                       int(bool(profile)), float(restart_drop))
+    if warm_params is not None:
+        o.warm_params = _ptr(warm_params)
+        if warm_u is not None:
+            for c in range(3):
+                o.warm_u[c] = _ptr(warm_u[c])
+    return o
 
 
 class Context:
     """sph_ctx bound to a device and (by default) torch's current stream."""
 
     def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise SphError(SPH_E_HIP, "no HIP device visible to torch")
         self.L = load()
         self.device = device
         h = C.c_void_p()
@@ -253,10 +279,59 @@ class Context:
                    n_true_checks=rep.n_true_checks, n_replaced=rep.n_replaced,
                    setup_ms=rep.setup_ms, iterate_ms=rep.iterate_ms, launches=rep.launches,
                    history_len=rep.history_len, mat_nnz=rep.mat_nnz, mat_slots=rep.mat_slots,
-                   apply_ms=rep.apply_ms, apply_launches=rep.apply_launches)
+                   apply_ms=rep.apply_ms, apply_launches=rep.apply_launches,
+                   warm_used=list(rep.warm_used), warm_rr=list(rep.warm_rr),
+                   plain_rr=list(rep.plain_rr), warm_scale=rep.warm_scale, warm_ms=rep.warm_ms)
         if history_cap > 0:
             out["history"] = [[hist[3 * i + c] for c in range(3)] for i in range(rep.history_len)]
         return out
+
+
+    # --- learned initial guess ----------------------------------------------
+    def sph_mlp_samples(self, nb: "Neighbors", particles: Particles, params: sph_visc_params,
+                        u: Sequence, rhs: Sequence, target: Optional[Sequence], samples) -> float:
+        """Fills samples (cuda float32, 3 n x 8) and returns U."""
+        us = (C.c_void_p * 3)(*[_ptr(t) for t in u])
+        bs = (C.c_void_p * 3)(*[_ptr(t) for t in rhs])
+        ts = (C.c_void_p * 3)(*[_ptr(t) for t in target]) if target is not None else None
+        U = C.c_double()
+        pc = particles.c()
+        self._check(self.L.sph_mlp_samples(self.h, nb.h, C.byref(pc), C.byref(params), us, bs, ts,
+                                           _ptr(samples), C.byref(U)), "sph_mlp_samples")
+        return U.value
+
+    def sph_mlp_warmstart(self, nb: "Neighbors", particles: Particles, params: sph_visc_params,
+                          prec: int, u: Sequence, rhs: Sequence, mlp_params, x0: Sequence) -> float:
+        us = (C.c_void_p * 3)(*[_ptr(t) for t in u])
+        bs = (C.c_void_p * 3)(*[_ptr(t) for t in rhs])
+        xs = (C.c_void_p * 3)(*[_ptr(t) for t in x0])
+        U = C.c_double()
+        pc = particles.c()
+        self._check(self.L.sph_mlp_warmstart(self.h, nb.h, C.byref(pc), C.byref(params), int(prec),
+                                             us, bs, _ptr(mlp_params), xs, C.byref(U)),
+                    "sph_mlp_warmstart")
+        return U.value
+
+    def sph_mlp_forward(self, samples, n: int, mlp_params, out):
+        self._check(self.L.sph_mlp_forward(self.h, _ptr(samples), int(n), _ptr(mlp_params),
+                                           _ptr(out)), "sph_mlp_forward")
+
+    def sph_mlp_grad(self, samples, idx, batch: int, mlp_params, grad) -> float:
+        loss = C.c_double()
+        self._check(self.L.sph_mlp_grad(self.h, _ptr(samples), _ptr(idx), int(batch),
+                                        _ptr(mlp_params), _ptr(grad), C.byref(loss)),
+                    "sph_mlp_grad")
+        return loss.value
+
+    def sph_mlp_train_step(self, samples, idx, batch: int, mlp_params, adam_m, adam_v, step: int,
+                           lr: float, want_loss: bool = True) -> Optional[float]:
+        loss = C.c_double()
+        self._check(self.L.sph_mlp_train_step(self.h, _ptr(samples), _ptr(idx), int(batch),
+                                              _ptr(mlp_params), _ptr(adam_m), _ptr(adam_v),
+                                              int(step), float(lr),
+                                              C.byref(loss) if want_loss else None),
+                    "sph_mlp_train_step")
+        return loss.value if want_loss else None
 
 
 class Neighbors:

@@ -24,8 +24,18 @@ def lib():
 def test_header_declares_the_entry_points():
     names = S.header_functions()
     for f in ("sph_build_neighbors", "sph_visc_apply", "sph_visc_solve", "sph_create",
-              "sph_destroy", "sph_neighbors_export", "sph_neighbors_free", "sph_status_str"):
+              "sph_destroy", "sph_neighbors_export", "sph_neighbors_free", "sph_status_str",
+              "sph_mlp_samples", "sph_mlp_warmstart", "sph_mlp_forward", "sph_mlp_grad",
+              "sph_mlp_train_step"):
         assert f in names
+
+
+def test_mlp_constants_agree():
+    from oracle import mlp as M
+    txt = open(S.HEADER).read()
+    assert f"#define SPH_MLP_NPARAM {M.NPARAM}" in txt
+    assert f"#define SPH_MLP_SAMPLE {M.SAMPLE}" in txt
+    assert S.SPH_MLP_NPARAM == M.NPARAM and S.SPH_MLP_SAMPLE == M.SAMPLE
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -47,18 +57,10 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.sph_create(None, 0, None) == -1
 
 
-STRUCTS = {
-    "sph_particles": ["n", "x", "y", "z", "mass", "rho", "mu", "type"],
-    "sph_domain": ["lo", "hi", "periodic", "h"],
-    "sph_visc_params": ["dt", "wall", "avg", "jacobi", "op_mode"],
-    "sph_solve_opts": ["tol", "max_iter", "variant", "floor", "true_res_period", "x0_given",
-                       "poll_every", "force_stall_iter", "force_stall_comp", "profile",
-                       "restart_drop"],
-    "sph_solve_report": ["iters", "status", "state", "stall_count", "rr", "bb", "tau2", "true_rr",
-                         "n_true_checks", "n_replaced", "history", "history_cap", "history_len",
-                         "setup_ms", "iterate_ms", "launches", "mat_nnz", "mat_slots", "apply_ms",
-                         "apply_launches"],
-}
+STRUCT_NAMES = ["sph_particles", "sph_domain", "sph_visc_params", "sph_solve_opts",
+                "sph_solve_report"]
+# every field of every ctypes mirror, in declaration order
+STRUCTS = {st: [f[0] for f in getattr(S, st)._fields_] for st in STRUCT_NAMES}
 
 
 def test_ctypes_layout_matches_c():
