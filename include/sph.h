@@ -55,7 +55,14 @@ typedef enum {
     SPH_E_NONFINITE = -5    /* non-finite right-hand side */
 } sph_status;
 
-enum { SPH_F64 = 0, SPH_F32 = 1 };                 /* vector / operator precision */
+/* Precision.  SPH_F64 and SPH_F32: operator, vectors and the caller's arrays
+ * in that precision (inner products and scalars are always FP64).
+ * SPH_MIXED (sph_visc_solve only): FP32 operator and Krylov vectors, the
+ * solution accumulated in FP64, and the caller's rhs, x and warm_u arrays in
+ * FP64.  An FP32 solution cannot carry a scaled residual much below
+ * 2^-24 A_rr relative to b, so for stiff rows only SPH_MIXED reaches tight
+ * tolerances with the FP32 operator. */
+enum { SPH_F64 = 0, SPH_F32 = 1, SPH_MIXED = 2 };
 enum { SPH_FLUID = 0, SPH_WALL = 1 };              /* particle type */
 enum { SPH_WALL_DYNAMIC = 0, SPH_WALL_DUMMY = 1 }; /* boundary model (Section "Boundary conditions") */
 enum { SPH_AVG_ARITH = 0, SPH_AVG_HARMONIC = 1 };  /* pairwise viscosity mean (Section "Discretized equations") */
@@ -212,11 +219,12 @@ sph_status sph_visc_apply(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *
                           void *const y[3]);
 
 /* Solve A V = B.  nb may be null, then dom must be given and the lists are
- * built inside the call.  rhs[c]: device, n values of the precision;
- * x[c]: device, n values; initial guess on entry if opts->x0_given, solution
- * on exit.  Vector updates and operator run in `prec`; every inner product
- * and every scalar of the recurrences is FP64 in both precisions.  With the
- * dummy model the wall rows of V are the viscous velocities. */
+ * built inside the call.  rhs[c]: device, n values of the precision (FP64
+ * for SPH_MIXED); x[c]: device, n values of the same; initial guess on
+ * entry if opts->x0_given, solution on exit.  Vector updates and operator
+ * run in `prec`; every inner product and every scalar of the recurrences is
+ * FP64 in all precisions.  With the dummy model the wall rows of V are the
+ * viscous velocities. */
 sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom,
                           const sph_particles *p, const sph_visc_params *params, int32_t prec,
                           const void *const rhs[3], void *const x[3], const sph_solve_opts *opts,
@@ -228,11 +236,12 @@ sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom
  * "Implementation notes"): a per-particle MLP
  *   x[4] -> 64 -> 64 -> 64 -> o[3] (ReLU), pred = o . B,
  * one sample per fluid particle and velocity component, with
- *   features x = (u_c / U, (u - A u)_c / U, log10 nu, log10(dt nu / h^2)),
- *   basis    B = (b_c / U, u_c / U, (u - A u)_c / U),  target t = V_c / U,
- * A the unscaled matrix of sph_visc_params, u the current velocity, b the
- * right-hand side, nu = mu / rho, U the RMS of b over fluid rows and
- * components.  The initial guess is x0_c = U pred on fluid rows; wall rows
+ *   features x = (u_c / U, d_c / U, log10 nu, log10(dt nu / h^2)),
+ *   basis    B = (b_c / U, u_c / U, d_c / U),  target t = V_c / U,
+ * d = D^-1 (u - A u) (the viscous increment of u scaled by the row's
+ * diagonal D = A_rr: one Jacobi correction), A the unscaled matrix of
+ * sph_visc_params, u the current velocity, b the right-hand side,
+ * nu = mu / rho, U the RMS of b over fluid rows and components.  The initial guess is x0_c = U pred on fluid rows; wall rows
  * take b (dynamic model) or satisfy their own row exactly, x0_w = b_w -
  * sum_a W x0_a / sum_a W (dummy model).
  * Parameters: one FP32 vector of SPH_MLP_NPARAM values (W1 [4][64], b1,

@@ -11,11 +11,15 @@ particle k and velocity component c:
   inc   = u - A u                 (A the unscaled viscous matrix, so inc is
                                    the implicit step's viscous increment
                                    dt * (Laplacian term) of the current u)
+  d     = inc / A_kk              (the increment scaled by the row's diagonal:
+                                   one Jacobi correction, of the size of u
+                                   however stiff the row is)
   U     = RMS of b over fluid rows and components (1 if that is 0)
-  x     = (u_c / U, inc_c / U, log10 nu_k, log10(dt nu_k / h^2)), nu = mu / rho
-  B     = (b_c / U, u_c / U, inc_c / U)
+  x     = (u_c / U, d_c / U, log10 nu_k, log10(dt nu_k / h^2)), nu = mu / rho
+  B     = (b_c / U, u_c / U, d_c / U)
   t     = V_c / U                 (V the converged solution, training only)
   x0_c  = U * (o . B)             with o = MLP(x)
+        = o0 b_c + o1 u_c + o2 d_c
 
 Wall rows of the start: a dynamic wall row is the identity, so x0 = b; a
 dummy wall row is satisfied exactly, x0_w = b_w - sum_a A_wa x0_a (the
@@ -46,6 +50,7 @@ def samples(op: Operator, u, b, mu, rho, ptype, target=None):
     n = u.shape[0]
     fl = np.asarray(ptype) == FLUID
     inc = u - op.apply(u)
+    d = inc / op.diag()[:, None]
     nfl = int(fl.sum())
     U = float(np.sqrt(np.sum(b[fl] ** 2) / (3.0 * nfl))) if nfl else 0.0
     if not (U > 0.0 and np.isfinite(U)):
@@ -53,12 +58,12 @@ def samples(op: Operator, u, b, mu, rho, ptype, target=None):
     nu = np.broadcast_to(np.asarray(mu, np.float64), (n,)) / np.broadcast_to(np.asarray(rho, np.float64), (n,))
     S = np.zeros((n, 3, 8))
     S[:, :, 0] = u / U
-    S[:, :, 1] = inc / U
+    S[:, :, 1] = d / U
     S[:, :, 2] = np.log10(nu)[:, None]
     S[:, :, 3] = np.log10(op.dt * nu / (op.h * op.h))[:, None]
     S[:, :, 4] = b / U
     S[:, :, 5] = u / U
-    S[:, :, 6] = inc / U
+    S[:, :, 6] = d / U
     if target is not None:
         S[:, :, 7] = np.asarray(target, dtype=np.float64) / U
     S[~fl] = 0.0
@@ -105,7 +110,7 @@ def select(op_scaled: Operator, b, x_plain, x_learn):
 
 def fixed_blend_params(o):
     """MLP parameters whose output is the constant o (W4 = 0, b4 = o): the
-    start is then the fixed blend o0 b + o1 u + o2 inc."""
+    start is then the fixed blend o0 b + o1 u + o2 d."""
     p = np.zeros(mlp.NPARAM, dtype=np.float32)
     p[mlp.NPARAM - 3:] = np.asarray(o, dtype=np.float32)
     return p

@@ -28,17 +28,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_props(int64_t n, const int32_
     ot[s] = t[o];
 }
 
-template <typename T>
+template <typename S, typename D>
 __global__ __launch_bounds__(kBlock) void k_gather_vec3(int64_t n, const int32_t* __restrict__ perm,
-                                                        const T* __restrict__ a, const T* __restrict__ b,
-                                                        const T* __restrict__ c, T* __restrict__ dst) {
+                                                        const S* __restrict__ a, const S* __restrict__ b,
+                                                        const S* __restrict__ c, D* __restrict__ dst) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int32_t o = perm[s];
-    V3<T> v;
-    v.x = a[o];
-    v.y = b[o];
-    v.z = c[o];
+    V3<D> v;
+    v.x = (D)a[o];
+    v.y = (D)b[o];
+    v.z = (D)c[o];
     st3(dst, s, v);
 }
 
@@ -73,9 +73,18 @@ sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p,
     return SPH_OK;
 }
 
+template <typename S, typename T>
+sph_status gather_vec3_cvt(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst) {
+    hipLaunchKernelGGL((k_gather_vec3<S, T>), dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0,
+                       ctx->stream, nb->n, nb->perm, (const S*)src[0], (const S*)src[1], (const S*)src[2], dst);
+    SPH_LAUNCHED("k_gather_vec3");
+    return SPH_OK;
+}
+template sph_status gather_vec3_cvt<double, float>(sph_ctx*, const sph_nbr*, const void* const[3], float*);
+
 template <typename T>
 sph_status gather_vec3(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst) {
-    hipLaunchKernelGGL(k_gather_vec3<T>, dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0, ctx->stream,
+    hipLaunchKernelGGL((k_gather_vec3<T, T>), dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0, ctx->stream,
                        nb->n, nb->perm, (const T*)src[0], (const T*)src[1], (const T*)src[2], dst);
     SPH_LAUNCHED("k_gather_vec3");
     return SPH_OK;

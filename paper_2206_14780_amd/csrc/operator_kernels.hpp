@@ -68,10 +68,11 @@ constexpr int kGroup = 8;  // entries per software-pipelined group
 // software-pipelined: the gathers of group g are issued before the column and
 // coefficient loads of group g + 1, so the L2 latency of the gathers and the
 // HBM latency of the matrix stream overlap.  RES accumulates in FP64 with the
-// FP64-accurate coefficients.
-template <typename T, bool RES, typename ACC>
+// FP64-accurate coefficients; x may then be of another precision XT than the
+// matrix (an FP64 solution under an FP32 operator).
+template <typename T, bool RES, typename ACC, typename XT = T>
 __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, int32_t row,
-                                const T* __restrict__ x, const V3<T>& xs, ACC& a0, ACC& a1, ACC& a2) {
+                                const XT* __restrict__ x, const V3<XT>& xs, ACC& a0, ACC& a1, ACC& a2) {
     int32_t cc[kGroup];
     T cw[kGroup];
     double cl[kGroup];
@@ -87,7 +88,7 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
         }
     }
     for (int32_t k0 = 0; k0 < width; k0 += kGroup) {
-        V3<T> xv[kGroup];
+        V3<XT> xv[kGroup];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) xv[u] = ld3(x, cc[u]);
         int32_t nc[kGroup];
@@ -130,10 +131,11 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
 // Cached operator: y_r = rs_r x_r + sum_k coef[r,k] (x[col[r,k]] - x_r).
 // One wavefront per 64-row slice; each block takes a contiguous range of
 // slices (XCD-aware order) and its waves interleave over it.  With kDotResid
-// the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead.
-template <typename T, int MODE>
+// the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead, and
+// x may be held in another precision XT.
+template <typename T, int MODE, typename XT = T>
 __global__ __launch_bounds__(kMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
-                                                          const T* __restrict__ x, T* __restrict__ y,
+                                                          const XT* __restrict__ x, T* __restrict__ y,
                                                           const T* __restrict__ w, const double* __restrict__ b64,
                                                           double* __restrict__ part) {
     if (halt && *halt) return;
@@ -155,10 +157,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_apply_sell(const int32_t* __restr
         if (row >= n) continue;
         const int64_t base = A.sl_ptr[s] + lane;
         const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
-        const V3<T> xs = ld3(x, row);
+        const V3<XT> xs = ld3(x, row);
         if constexpr (RES) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            sell_row<T, true>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
+            sell_row<T, true, double, XT>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
             const double d = A.rs64[row];
             const V3<double> bb = ld3(b64, row);
             const double r0 = bb.x - (d * (double)xs.x + a0);
@@ -235,10 +237,11 @@ __device__ inline void row_apply_otf(const NbrView& nv, const PartView& pv, cons
 }
 
 // On-the-fly operator over rows in cell order; with kDotResid it writes
-// y = b64 - A x instead (FP64 residual rounded to T) and its squared norm.
-template <typename T, int MODE>
+// y = b64 - A x instead (FP64 residual rounded to T) and its squared norm,
+// x then being of precision XT.
+template <typename T, int MODE, typename XT = T>
 __global__ __launch_bounds__(kMaxBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
-                                                         OpParams op, const T* __restrict__ x, T* __restrict__ y,
+                                                         OpParams op, const XT* __restrict__ x, T* __restrict__ y,
                                                          const T* __restrict__ w, const double* __restrict__ b64,
                                                          double* __restrict__ part) {
     if (halt && *halt) return;
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_apply_otf(const int32_t* __restri
     const int64_t r1 = min(r0 + rpb, nv.n);
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
         double yv[3];
-        row_apply_otf<T>(nv, pv, op, x, (int32_t)r, yv);
+        row_apply_otf<XT>(nv, pv, op, x, (int32_t)r, yv);
         if constexpr (MODE == kDotResid) {
             const V3<double> bb = ld3(b64, r);
             yv[0] = bb.x - yv[0];

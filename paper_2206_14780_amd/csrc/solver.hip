@@ -297,11 +297,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32
 }
 
 // omega_i = (s . A s)/(A s . A s); x = x + alpha p + omega s; r = s - omega A s;
-// partials of r0hat . r and r . r.
-template <typename T, int KA>
+// partials of r0hat . r and r . r.  x is held in X (T, or FP64 under an FP32
+// operator: then the update is evaluated in FP64).
+template <typename T, int KA, typename X>
 __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                      const double* __restrict__ part, int32_t nblk, int64_t n,
-                                                     T* __restrict__ x, const T* __restrict__ p,
+                                                     X* __restrict__ x, const T* __restrict__ p,
                                                      const T* __restrict__ s, const T* __restrict__ as,
                                                      T* __restrict__ r, const T* __restrict__ rh0,
                                                      double* __restrict__ part_out) {
@@ -339,19 +340,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
     const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const V3<T> xv = ld3(x, i), pv = ld3(p, i), sv = ld3(s, i), av = ld3(as, i), hv = ld3(rh0, i);
-        const T xx[3] = {xv.x, xv.y, xv.z}, pp[3] = {pv.x, pv.y, pv.z}, ss[3] = {sv.x, sv.y, sv.z};
+        const V3<X> xv = ld3(x, i);
+        const V3<T> pv = ld3(p, i), sv = ld3(s, i), av = ld3(as, i), hv = ld3(rh0, i);
+        const X xx[3] = {xv.x, xv.y, xv.z};
+        const T pp[3] = {pv.x, pv.y, pv.z}, ss[3] = {sv.x, sv.y, sv.z};
         const T aa[3] = {av.x, av.y, av.z}, hh[3] = {hv.x, hv.y, hv.z};
-        T xo[3], ro[3];
+        X xo[3];
+        T ro[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T t = xx[c] + A[c] * pp[c];
-            xo[c] = t + W[c] * ss[c];
+            if constexpr (sizeof(X) == sizeof(T)) {
+                const T t = xx[c] + A[c] * pp[c];
+                xo[c] = t + W[c] * ss[c];
+            } else {
+                const double t = (double)xx[c] + al[c] * (double)pp[c];
+                xo[c] = t + om[c] * (double)ss[c];
+            }
             ro[c] = ss[c] - W[c] * aa[c];
             acc[c] += (double)hh[c] * (double)ro[c];
             acc[3 + c] += (double)ro[c] * (double)ro[c];
         }
-        st3(x, i, V3<T>{xo[0], xo[1], xo[2]});
+        st3(x, i, V3<X>{xo[0], xo[1], xo[2]});
         st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
     }
     write_partials<kKp>(acc, lds, part_out);
@@ -452,11 +461,12 @@ __global__ void k_ctl_init(Ctl* ctl) {
     }
 }
 
-// rhs in caller order -> b64 = D^-1 B in FP64 and b = rounded copy, cell order.
-template <typename T>
+// rhs in caller order (precision C) -> b64 = D^-1 B in FP64 and b = rounded
+// copy, cell order.
+template <typename T, typename C>
 __global__ __launch_bounds__(kBlock) void k_prep_rhs(int64_t n, const int32_t* __restrict__ perm,
-                                                     const T* __restrict__ b0, const T* __restrict__ b1,
-                                                     const T* __restrict__ b2, const double* __restrict__ diag64,
+                                                     const C* __restrict__ b0, const C* __restrict__ b1,
+                                                     const C* __restrict__ b2, const double* __restrict__ diag64,
                                                      int32_t jacobi, double* __restrict__ b64,
                                                      T* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -483,7 +493,10 @@ sph_status read_ctl(sph_ctx* ctx, const Ctl* d, Ctl* h) {
     return SPH_OK;
 }
 
-template <typename T>
+// T: precision of the operator and of the Krylov vectors; X: precision of
+// the solution and of the caller's arrays (X = T, or FP64 under an FP32
+// operator).
+template <typename T, typename X>
 struct Solver {
     sph_ctx* ctx;
     const sph_nbr* nb;
@@ -493,7 +506,8 @@ struct Solver {
     Sell<T> sell{};
     const double* diag64 = nullptr;
     Launch L;
-    T *b, *x, *r, *rh0, *p, *ap, *s, *as, *tmp;
+    T *b, *r, *rh0, *p, *ap, *s, *as, *tmp;
+    X* x;
     double* b64;
     double *pa1, *pa2, *pk3, *ptr, *pchk;
     Ctl* ctl;
@@ -525,15 +539,16 @@ struct Solver {
     dim3 gs() const { return dim3(L.grid_stream); }
     dim3 bs() const { return dim3(L.block_stream); }
 
-    // y = A x fused with the dot products of mode MODE
-    template <int MODE>
-    void apply(const int32_t* halt, const T* xin, T* yout, const T* w, double* part) {
+    // y = A x fused with the dot products of mode MODE (x of precision XT:
+    // T, or X for the true residual)
+    template <int MODE, typename XT = T>
+    void apply(const int32_t* halt, const XT* xin, T* yout, const T* w, double* part) {
         if (mode == SPH_OP_CACHED)
-            hipLaunchKernelGGL((k_apply_sell<T, MODE>), ga(), ba(), 0, ctx->stream, halt, L.n, sell, xin, yout, w,
-                               (const double*)b64, part);
+            hipLaunchKernelGGL((k_apply_sell<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, L.n, sell, xin, yout,
+                               w, (const double*)b64, part);
         else
-            hipLaunchKernelGGL((k_apply_otf<T, MODE>), ga(), ba(), 0, ctx->stream, halt, nb->view(), pv, op, xin,
-                               yout, w, (const double*)b64, part);
+            hipLaunchKernelGGL((k_apply_otf<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, nb->view(), pv, op,
+                               xin, yout, w, (const double*)b64, part);
         ++launches;
     }
 
@@ -554,12 +569,12 @@ struct Solver {
         if (sc.variant == SPH_STANDARD) {
             apply<kDotA2Std>(halt, s, as, nullptr, pa2);
             if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 9>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
+            hipLaunchKernelGGL((k_close<T, 9, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
                                p, s, as, r, rh0, pk3);
         } else {
             apply<kDotA2>(halt, s, as, nullptr, pa2);
             if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 6>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
+            hipLaunchKernelGGL((k_close<T, 6, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
                                p, s, as, r, rh0, pk3);
         }
         launches += 3;
@@ -569,7 +584,7 @@ struct Solver {
     }
 
     // FP64-accurate b - A x of the current x into tmp, partials into `part`.
-    void true_residual(const int32_t* halt, double* part) { apply<kDotResid>(halt, x, tmp, nullptr, part); }
+    void true_residual(const int32_t* halt, double* part) { apply<kDotResid, X>(halt, x, tmp, nullptr, part); }
 
     void host_check() {
         true_residual(nullptr, pchk);
@@ -582,11 +597,11 @@ struct Solver {
     }
 };
 
-template <typename T>
+template <typename T, typename X>
 sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part, const sph_visc_params* vp,
                       int32_t prec, const void* const rhs[3], void* const xout[3], const sph_solve_opts* o,
                       sph_solve_report* rep) {
-    Solver<T> S;
+    Solver<T, X> S;
     S.ctx = ctx;
     S.nb = nb;
     S.mode = vp->op_mode;
@@ -609,7 +624,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     }
     const size_t v3 = (size_t)n * 3;
     SPH_TRY(ctx->ensure_t(kVecB, v3, &S.b));
-    SPH_TRY(ctx->ensure_t(kVecX, v3, &S.x));
+    SPH_TRY(ctx->ensure_t(kVecX, v3, &S.x));  // X
     SPH_TRY(ctx->ensure_t(kVecR, v3, &S.r));
     SPH_TRY(ctx->ensure_t(kVecRh0, v3, &S.rh0));
     SPH_TRY(ctx->ensure_t(kVecP, v3, &S.p));
@@ -631,9 +646,10 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     SPH_TRY(ctx->ensure_t(kStallHist, (size_t)hist_rows * 3, &S.stallhist));
 
     S.sc.tol2 = o->tol * o->tol;
-    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : (prec == SPH_F32 ? 1e-6 : 0.0);
+    const bool vec32 = sizeof(T) == 4;
+    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : (vec32 ? 1e-6 : 0.0);
     S.sc.tr_blocks = L.grid_apply;
-    S.sc.floor_ = o->floor >= 0.0 ? o->floor : (prec == SPH_F32 ? (double)FLT_MIN : DBL_MIN);
+    S.sc.floor_ = o->floor >= 0.0 ? o->floor : (vec32 ? (double)FLT_MIN : DBL_MIN);
     S.sc.max_iter = o->max_iter;
     S.sc.variant = o->variant;
     S.sc.true_res_period = o->true_res_period;
@@ -642,8 +658,8 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     S.sc.hist_cap = hist_rows;
 
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, ctx->stream, S.ctl);
-    hipLaunchKernelGGL(k_prep_rhs<T>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
-                       nb->perm, (const T*)rhs[0], (const T*)rhs[1], (const T*)rhs[2], S.diag64, S.op.jacobi,
+    hipLaunchKernelGGL((k_prep_rhs<T, X>), dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
+                       nb->perm, (const X*)rhs[0], (const X*)rhs[1], (const X*)rhs[2], S.diag64, S.op.jacobi,
                        S.b64, S.b);
     S.launches += 2;
     const T* r0 = nullptr;
@@ -655,32 +671,35 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         SPH_TRY(ctx->ensure_t(kWarmInfo, kWiSize, &winfo));
         const void* uu[3];
         for (int c = 0; c < 3; ++c) uu[c] = o->warm_u[c] ? o->warm_u[c] : rhs[c];
-        SPH_TRY(gather_vec3<T>(ctx, nb, uu, S.p));
+        if constexpr (sizeof(X) == sizeof(T))
+            SPH_TRY(gather_vec3<T>(ctx, nb, uu, S.p));
+        else
+            SPH_TRY((gather_vec3_cvt<X, T>(ctx, nb, uu, S.p)));
         const WarmOp<T> w{nb, S.pv, S.op, S.mode, &S.sell, S.diag64};
-        SPH_TRY(warm_learned<T>(ctx, w, rhs, S.p, o->warm_params, S.s, winfo));
+        SPH_TRY((warm_learned<T, X>(ctx, w, rhs, S.p, o->warm_params, S.s, winfo)));
         double* pl = S.pchk;
         double* pp = S.pchk + 3 * (size_t)L.grid_apply;
-        S.template apply<kDotResid>(nullptr, S.s, S.as, nullptr, pl);
+        S.template apply<kDotResid, T>(nullptr, S.s, S.as, nullptr, pl);
         if (o->x0_given) {
-            SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
-            S.template apply<kDotResid>(nullptr, S.x, S.tmp, nullptr, pp);
+            SPH_TRY(gather_vec3<X>(ctx, nb, (const void* const*)xout, S.x));
+            S.template apply<kDotResid, X>(nullptr, S.x, S.tmp, nullptr, pp);
         } else {
-            SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
+            SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
             SPH_TRY(warm_zero_rr(ctx, n, L.grid_apply, S.b64, pp));
         }
-        SPH_TRY(warm_select<T>(ctx, n, L.grid_stream, L.block_stream, pl, pp, L.grid_apply, o->x0_given, S.x,
-                               S.s, S.as, S.b, S.tmp, winfo));
+        SPH_TRY((warm_select<T, X>(ctx, n, L.grid_stream, L.block_stream, pl, pp, L.grid_apply, o->x0_given, S.x,
+                                   S.s, S.as, S.b, S.tmp, winfo)));
         r0 = S.tmp;
         S.launches += 11;
         SPH_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
     } else if (o->x0_given) {
         // r0 = b - A x0 with the FP64-accurate operator
-        SPH_TRY(gather_vec3<T>(ctx, nb, (const void* const*)xout, S.x));
+        SPH_TRY(gather_vec3<X>(ctx, nb, (const void* const*)xout, S.x));
         S.true_residual(nullptr, S.pchk);
         r0 = S.tmp;
         ++S.launches;
     } else {
-        SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(T) * v3, ctx->stream));
+        SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
     }
     SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
     SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
@@ -748,7 +767,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         hipLaunchKernelGGL(k_final_trr, dim3(1), dim3(kMaxBlock), 0, ctx->stream, S.ctl, S.pchk, L.grid_apply);
         S.launches += 1;
     }
-    SPH_TRY(scatter_vec3<T>(ctx, nb, S.x, xout));
+    SPH_TRY(scatter_vec3<X>(ctx, nb, S.x, xout));
     ++S.launches;
     SPH_LAUNCHED("solve finish");
     SPH_HIP(hipEventRecord(e2, ctx->stream));
@@ -844,15 +863,20 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
     }
     if (nb->device != ctx->device) return ctx->fail(SPH_E_ARG, "visc_solve: handle of another device");
     sph_status st = check_particles(ctx, nb, p);
-    if (st == SPH_OK) st = check_params(ctx, params, prec);
+    // SPH_MIXED: FP32 operator and vectors (checked as SPH_F32), FP64 solution
+    if (st == SPH_OK) st = check_params(ctx, params, prec == SPH_MIXED ? SPH_F32 : prec);
     if (st == SPH_OK) {
         double* hist_keep = report->history;
         int32_t cap_keep = report->history_cap;
         std::memset(report, 0, sizeof(*report));
         report->history = hist_keep;
         report->history_cap = cap_keep;
-        st = prec == SPH_F64 ? solve_impl<double>(ctx, nb, p, params, prec, rhs, x, opts, report)
-                             : solve_impl<float>(ctx, nb, p, params, prec, rhs, x, opts, report);
+        if (prec == SPH_F64)
+            st = solve_impl<double, double>(ctx, nb, p, params, prec, rhs, x, opts, report);
+        else if (prec == SPH_F32)
+            st = solve_impl<float, float>(ctx, nb, p, params, prec, rhs, x, opts, report);
+        else
+            st = solve_impl<float, double>(ctx, nb, p, params, prec, rhs, x, opts, report);
     }
     if (own) sph_neighbors_free(own);
     return st;

@@ -246,6 +246,9 @@ sph_status scan_i64(sph_ctx* ctx, const int64_t* in, int64_t* out, int64_t n);
 sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out);
 template <typename T>
 sph_status gather_vec3(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst);
+// The same from caller arrays of precision S into cell-order T (S = double, T = float).
+template <typename S, typename T>
+sph_status gather_vec3_cvt(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst);
 template <typename T>
 sph_status scatter_vec3(sph_ctx* ctx, const sph_nbr* nb, const T* src, void* const dst[3]);
 // Builds the cached matrix; *nnz / *slots (host, optional) receive the

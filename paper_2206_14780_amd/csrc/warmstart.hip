@@ -5,9 +5,10 @@
 // "Conclusions and future work" and "Implementation notes").
 //
 // One sample per fluid row r and component c (wall rows: all zero):
-//   inc = u - A u = -(sum of the off-diagonal terms of A applied to u - u_r)
-//   x = (u_c / U, inc_c / U, log10 nu_r, log10(dt nu_r / h^2)),  nu = mu / rho
-//   B = (b_c / U, u_c / U, inc_c / U),  t = V_c / U (training only)
+//   d = (u - A u) / A_rr = -(1/A_rr) sum_k A_rk (u_k - u_r)   (one Jacobi
+//       correction of u: the viscous increment scaled by the row's diagonal)
+//   x = (u_c / U, d_c / U, log10 nu_r, log10(dt nu_r / h^2)),  nu = mu / rho
+//   B = (b_c / U, u_c / U, d_c / U),  t = V_c / U (training only)
 // with U the RMS of b over fluid rows and components (1 if that is 0).
 #include <algorithm>
 #include <cmath>
@@ -23,16 +24,16 @@ namespace {
 
 constexpr int kStatBlocks = 256;
 
-template <typename T>
+template <typename C>
 struct Rhs {
     const int32_t* perm;  // cell -> caller order
-    const T* b[3];        // caller order
+    const C* b[3];        // caller order, caller precision
     __device__ double at(int64_t r, int c) const { return (double)b[c][perm[r]]; }
 };
 
 // Partial sums of b.b over fluid rows and of the fluid row count.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_stats(int64_t n, Rhs<T> rhs, const uint8_t* __restrict__ type,
+template <typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_stats(int64_t n, Rhs<C> rhs, const uint8_t* __restrict__ type,
                                                        double* __restrict__ part) {
     __shared__ double lds[2 * kMaxWaves];
     double acc[2] = {0.0, 0.0};
@@ -59,9 +60,9 @@ __global__ __launch_bounds__(kBlock) void k_warm_scale(const double* __restrict_
     }
 }
 
-// Writes the 3 samples of row r given inc (u - A u).
-template <typename T>
-__device__ inline void warm_write(int64_t r, const Rhs<T>& rhs, const V3<T>& u, const double (&inc)[3],
+// Writes the 3 samples of row r given d.
+template <typename T, typename C>
+__device__ inline void warm_write(int64_t r, const Rhs<C>& rhs, const V3<T>& u, const double (&d)[3],
                                   const PartView& pv, double dt, double h, double U,
                                   const double* const* tgt, float* __restrict__ out) {
     const double nu = pv.mu[r] / pv.rho[r];
@@ -70,7 +71,7 @@ __device__ inline void warm_write(int64_t r, const Rhs<T>& rhs, const V3<T>& u, 
     const double uu[3] = {(double)u.x, (double)u.y, (double)u.z};
     for (int c = 0; c < 3; ++c) {
         float* o = out + c * kSample;
-        const double uc = uu[c] / U, ic = inc[c] / U;
+        const double uc = uu[c] / U, ic = d[c] / U;
         o[0] = (float)uc;
         o[1] = (float)ic;
         o[2] = f2;
@@ -82,14 +83,14 @@ __device__ inline void warm_write(int64_t r, const Rhs<T>& rhs, const V3<T>& u, 
     }
 }
 
-template <typename T>
+template <typename T, typename C>
 struct FeatArgs {
     int64_t n;
-    Rhs<T> rhs;
+    Rhs<C> rhs;
     const T* u;              // cell order, AoS
     PartView pv;
     double dt, h;
-    const double* diag64;    // D (used when the coefficients are Jacobi scaled)
+    const double* diag64;    // D = A_rr
     int32_t jacobi;
     const double* info;      // U at kWiU
     const double* tgt[3];    // caller order, or null
@@ -98,8 +99,8 @@ struct FeatArgs {
     float* samples;
 };
 
-template <typename T>
-__device__ inline float* sample_row(const FeatArgs<T>& a, int64_t r) {
+template <typename T, typename C>
+__device__ inline float* sample_row(const FeatArgs<T, C>& a, int64_t r) {
     const int64_t k = a.orig_order ? (int64_t)a.rhs.perm[r] : r;
     return a.samples + k * 3 * kSample;
 }
@@ -108,9 +109,10 @@ __device__ inline void zero_row(float* o) {
     for (int k = 0; k < 3 * kSample; ++k) o[k] = 0.f;
 }
 
-// Cached matrix: inc = -D sum_k c_k (u_k - u_r) (c = A_rk / D with Jacobi, A_rk without).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T> a, Sell<T> A) {
+// Cached matrix: d = -sum_k c_k (u_k - u_r) with c = A_rk / D (Jacobi
+// scaled), or -(1/D) sum_k c_k (u_k - u_r) with c = A_rk.
+template <typename T, typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T, C> a, Sell<T> A) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.n) return;
     float* o = sample_row(a, r);
@@ -124,14 +126,17 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T> a, Sell<T
     const V3<T> us = ld3(a.u, r);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     sell_row<T, true>(A, base, width, (int32_t)r, a.u, us, s0, s1, s2);
-    const double sc = a.jacobi ? -a.diag64[r] : -1.0;
-    const double inc[3] = {sc * s0, sc * s1, sc * s2};
-    warm_write<T>(r, a.rhs, us, inc, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+    double d[3] = {-s0, -s1, -s2};
+    if (!a.jacobi) {
+        const double D = a.diag64[r];
+        for (int c = 0; c < 3; ++c) d[c] /= D;
+    }
+    warm_write<T, C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
 }
 
-// On-the-fly operator: inc = dt sum_a w_ra (u_a - u_r).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_feat_otf(FeatArgs<T> a, NbrView nv, int32_t avg) {
+// On-the-fly operator: d = dt sum_a w_ra (u_a - u_r) / D.
+template <typename T, typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_feat_otf(FeatArgs<T, C> a, NbrView nv, int32_t avg) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.n) return;
     float* o = sample_row(a, r);
@@ -148,13 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_otf(FeatArgs<T> a, NbrView
         s1 += w * ((double)uk.y - (double)us.y);
         s2 += w * ((double)uk.z - (double)us.z);
     });
-    const double inc[3] = {a.dt * s0, a.dt * s1, a.dt * s2};
-    warm_write<T>(r, a.rhs, us, inc, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+    const double f = a.dt / a.diag64[r];
+    const double d[3] = {f * s0, f * s1, f * s2};
+    warm_write<T, C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
 }
 
 // x = U pred on fluid rows, b on dynamic walls, 0 on dummy walls (filled next).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_x0(int64_t n, Rhs<T> rhs, const uint8_t* __restrict__ type,
+template <typename T, typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_x0(int64_t n, Rhs<C> rhs, const uint8_t* __restrict__ type,
                                                     int32_t wall, const float* __restrict__ mlp_out,
                                                     const double* __restrict__ info, T* __restrict__ x) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_warm_x0(int64_t n, Rhs<T> rhs, const
 
 // Dummy wall rows: x_w = b_w - sum_a A_wa x_a (the stored entries of a dummy
 // wall row are its fluid neighbours' normalised kernel values; D = 1 there).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_wall_sell(int64_t n, Rhs<T> rhs, const uint8_t* __restrict__ type,
+template <typename T, typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_wall_sell(int64_t n, Rhs<C> rhs, const uint8_t* __restrict__ type,
                                                            Sell<T> A, T* __restrict__ x) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || type[r] == SPH_FLUID) return;
@@ -187,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_warm_wall_sell(int64_t n, Rhs<T> rhs
     st3(x, r, V3<T>{(T)(rhs.at(r, 0) - s0), (T)(rhs.at(r, 1) - s1), (T)(rhs.at(r, 2) - s2)});
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_warm_wall_otf(Rhs<T> rhs, NbrView nv, const uint8_t* __restrict__ type,
+template <typename T, typename C>
+__global__ __launch_bounds__(kBlock) void k_warm_wall_otf(Rhs<C> rhs, NbrView nv, const uint8_t* __restrict__ type,
                                                           T* __restrict__ x) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nv.n || type[r] == SPH_FLUID) return;
@@ -211,22 +217,23 @@ __global__ __launch_bounds__(kBlock) void k_warm_wall_otf(Rhs<T> rhs, NbrView nv
     st3(x, r, V3<T>{(T)v[0], (T)v[1], (T)v[2]});
 }
 
-template <typename T>
-sph_status launch_features(sph_ctx* ctx, const WarmOp<T>& w, const FeatArgs<T>& a) {
+template <typename T, typename C>
+sph_status launch_features(sph_ctx* ctx, const WarmOp<T>& w, const FeatArgs<T, C>& a) {
     const unsigned grid = (unsigned)ceil_div(a.n, kBlock);
     if (w.mode == SPH_OP_CACHED)
-        hipLaunchKernelGGL(k_warm_feat_sell<T>, dim3(grid), dim3(kBlock), 0, ctx->stream, a, *w.sell);
+        hipLaunchKernelGGL((k_warm_feat_sell<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, a, *w.sell);
     else
-        hipLaunchKernelGGL(k_warm_feat_otf<T>, dim3(grid), dim3(kBlock), 0, ctx->stream, a, w.nb->view(), w.op.avg);
+        hipLaunchKernelGGL((k_warm_feat_otf<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, a, w.nb->view(),
+                           w.op.avg);
     SPH_LAUNCHED("k_warm_feat");
     return SPH_OK;
 }
 
-template <typename T>
-Rhs<T> make_rhs(const sph_nbr* nb, const void* const rhs[3]) {
-    Rhs<T> r;
+template <typename C>
+Rhs<C> make_rhs(const sph_nbr* nb, const void* const rhs[3]) {
+    Rhs<C> r;
     r.perm = nb->perm;
-    for (int c = 0; c < 3; ++c) r.b[c] = static_cast<const T*>(rhs[c]);
+    for (int c = 0; c < 3; ++c) r.b[c] = static_cast<const C*>(rhs[c]);
     return r;
 }
 
@@ -250,10 +257,10 @@ __global__ __launch_bounds__(kBlock) void k_warm_bb(int64_t n, const double* __r
 // r.r is smaller than the plain start's; otherwise r0 <- rp (plain start
 // given) or b (zero start).  Every block reduces both sets of partials in
 // the same fixed order, so all blocks take the same decision.
-template <typename T>
+template <typename T, typename X>
 __global__ __launch_bounds__(kMaxBlock) void k_warm_select(int64_t n, const double* __restrict__ pl,
                                                            const double* __restrict__ pp, int nparts,
-                                                           int32_t plain_given, T* __restrict__ x,
+                                                           int32_t plain_given, X* __restrict__ x,
                                                            const T* __restrict__ xl, const T* __restrict__ rl,
                                                            const T* __restrict__ b, T* __restrict__ r0,
                                                            double* __restrict__ info) {
@@ -271,11 +278,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_warm_select(int64_t n, const doub
         }
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        V3<T> xv = ld3(x, i), rv = plain_given ? ld3(r0, i) : ld3(b, i);
+        V3<X> xv = ld3(x, i);
+        V3<T> rv = plain_given ? ld3(r0, i) : ld3(b, i);
         const V3<T> xlv = ld3(xl, i), rlv = ld3(rl, i);
-        if (use[0]) { xv.x = xlv.x; rv.x = rlv.x; }
-        if (use[1]) { xv.y = xlv.y; rv.y = rlv.y; }
-        if (use[2]) { xv.z = xlv.z; rv.z = rlv.z; }
+        if (use[0]) { xv.x = (X)xlv.x; rv.x = rlv.x; }
+        if (use[1]) { xv.y = (X)xlv.y; rv.y = rlv.y; }
+        if (use[2]) { xv.z = (X)xlv.z; rv.z = rlv.z; }
         st3(x, i, xv);
         st3(r0, i, rv);
     }
@@ -289,34 +297,36 @@ sph_status warm_zero_rr(sph_ctx* ctx, int64_t n, int32_t nblk, const double* b64
     return SPH_OK;
 }
 
-template <typename T>
+template <typename T, typename X>
 sph_status warm_select(sph_ctx* ctx, int64_t n, int32_t grid, int32_t block, const double* pl, const double* pp,
-                       int32_t nparts, int32_t plain_given, T* x, const T* xl, const T* rl, const T* b, T* r0,
+                       int32_t nparts, int32_t plain_given, X* x, const T* xl, const T* rl, const T* b, T* r0,
                        double* info) {
-    hipLaunchKernelGGL(k_warm_select<T>, dim3(grid), dim3(block), 0, ctx->stream, n, pl, pp, nparts, plain_given, x,
-                       xl, rl, b, r0, info);
+    hipLaunchKernelGGL((k_warm_select<T, X>), dim3(grid), dim3(block), 0, ctx->stream, n, pl, pp, nparts,
+                       plain_given, x, xl, rl, b, r0, info);
     SPH_LAUNCHED("k_warm_select");
     return SPH_OK;
 }
 
-template sph_status warm_select<float>(sph_ctx*, int64_t, int32_t, int32_t, const double*, const double*, int32_t,
-                                       int32_t, float*, const float*, const float*, const float*, float*, double*);
-template sph_status warm_select<double>(sph_ctx*, int64_t, int32_t, int32_t, const double*, const double*, int32_t,
-                                        int32_t, double*, const double*, const double*, const double*, double*,
-                                        double*);
+#define SPH_WARM_SELECT(T, X)                                                                                   \
+    template sph_status warm_select<T, X>(sph_ctx*, int64_t, int32_t, int32_t, const double*, const double*,     \
+                                          int32_t, int32_t, X*, const T*, const T*, const T*, T*, double*);
+SPH_WARM_SELECT(float, float)
+SPH_WARM_SELECT(double, double)
+SPH_WARM_SELECT(float, double)
+#undef SPH_WARM_SELECT
 
-template <typename T>
+template <typename T, typename C>
 sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
                         const double* const tgt[3], int32_t orig_order, float* samples, double* info) {
     const int64_t n = w.nb->n;
     double* part = nullptr;
     SPH_TRY(ctx->ensure_t(kWarmPart, 2 * kStatBlocks, &part));
-    const Rhs<T> rb = make_rhs<T>(w.nb, rhs);
+    const Rhs<C> rb = make_rhs<C>(w.nb, rhs);
     const int sb = (int)std::min<int64_t>(kStatBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
-    hipLaunchKernelGGL(k_warm_stats<T>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type, part);
+    hipLaunchKernelGGL(k_warm_stats<C>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type, part);
     hipLaunchKernelGGL(k_warm_scale, dim3(1), dim3(kBlock), 0, ctx->stream, (const double*)part, sb, info);
     SPH_LAUNCHED("k_warm_stats/k_warm_scale");
-    FeatArgs<T> a;
+    FeatArgs<T, C> a;
     a.n = n;
     a.rhs = rb;
     a.u = u;
@@ -330,42 +340,43 @@ sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[
     for (int c = 0; c < 3; ++c) a.tgt[c] = tgt ? tgt[c] : nullptr;
     a.orig_order = orig_order;
     a.samples = samples;
-    return launch_features<T>(ctx, w, a);
+    return launch_features<T, C>(ctx, w, a);
 }
 
-template <typename T>
+template <typename T, typename C>
 sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
                         const float* params, T* x, double* info) {
     const int64_t n = w.nb->n;
     float *S = nullptr, *O = nullptr;
     SPH_TRY(ctx->ensure_t(kWarmS, (size_t)n * 3 * kSample, &S));
     SPH_TRY(ctx->ensure_t(kWarmO, (size_t)n * 3 * 4, &O));
-    SPH_TRY(warm_samples<T>(ctx, w, rhs, u, nullptr, 0, S, info));
+    SPH_TRY((warm_samples<T, C>(ctx, w, rhs, u, nullptr, 0, S, info)));
     SPH_TRY(mlp::forward(ctx, S, n * 3, params, O));
-    const Rhs<T> rb = make_rhs<T>(w.nb, rhs);
+    const Rhs<C> rb = make_rhs<C>(w.nb, rhs);
     const unsigned grid = (unsigned)ceil_div(n, kBlock);
-    hipLaunchKernelGGL(k_warm_x0<T>, dim3(grid), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type, w.op.wall,
+    hipLaunchKernelGGL((k_warm_x0<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type, w.op.wall,
                        (const float*)O, (const double*)info, x);
     if (w.op.wall == SPH_WALL_DUMMY) {
         if (w.mode == SPH_OP_CACHED)
-            hipLaunchKernelGGL(k_warm_wall_sell<T>, dim3(grid), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type,
+            hipLaunchKernelGGL((k_warm_wall_sell<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type,
                                *w.sell, x);
         else
-            hipLaunchKernelGGL(k_warm_wall_otf<T>, dim3(grid), dim3(kBlock), 0, ctx->stream, rb, w.nb->view(),
+            hipLaunchKernelGGL((k_warm_wall_otf<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, rb, w.nb->view(),
                                w.pv.type, x);
     }
     SPH_LAUNCHED("k_warm_x0/k_warm_wall");
     return SPH_OK;
 }
 
-template sph_status warm_samples<float>(sph_ctx*, const WarmOp<float>&, const void* const[3], const float*,
-                                        const double* const[3], int32_t, float*, double*);
-template sph_status warm_samples<double>(sph_ctx*, const WarmOp<double>&, const void* const[3], const double*,
-                                         const double* const[3], int32_t, float*, double*);
-template sph_status warm_learned<float>(sph_ctx*, const WarmOp<float>&, const void* const[3], const float*,
-                                        const float*, float*, double*);
-template sph_status warm_learned<double>(sph_ctx*, const WarmOp<double>&, const void* const[3], const double*,
-                                         const float*, double*, double*);
+#define SPH_WARM_INST(T, C)                                                                                    \
+    template sph_status warm_samples<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const T*,           \
+                                           const double* const[3], int32_t, float*, double*);                    \
+    template sph_status warm_learned<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const T*,           \
+                                           const float*, T*, double*);
+SPH_WARM_INST(float, float)
+SPH_WARM_INST(double, double)
+SPH_WARM_INST(float, double)
+#undef SPH_WARM_INST
 
 }  // namespace sph
 
@@ -412,7 +423,7 @@ sph_status warmstart_entry(sph_ctx* ctx, const sph_nbr* nb, const sph_particles*
     SPH_TRY(prepare<T>(ctx, nb, p, v, u, &w, &sell, &ucell, &info));
     T* x = nullptr;
     SPH_TRY(ctx->ensure_t(kApplyOut, (size_t)nb->n * 3, &x));
-    SPH_TRY(warm_learned<T>(ctx, w, rhs, ucell, params, x, info));
+    SPH_TRY((warm_learned<T, T>(ctx, w, rhs, ucell, params, x, info)));
     SPH_TRY(scatter_vec3<T>(ctx, nb, x, x0));
     if (U) {
         SPH_HIP(hipMemcpyAsync(U, info + kWiU, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -439,7 +450,7 @@ extern "C" sph_status sph_mlp_samples(sph_ctx* ctx, const sph_nbr* nb, const sph
     double* ucell = nullptr;
     double* info = nullptr;
     SPH_TRY(prepare<double>(ctx, nb, p, params, (const void* const*)u, &w, &sell, &ucell, &info));
-    SPH_TRY(warm_samples<double>(ctx, w, (const void* const*)rhs, ucell, target, 1, samples, info));
+    SPH_TRY((warm_samples<double, double>(ctx, w, (const void* const*)rhs, ucell, target, 1, samples, info)));
     double Uh = 0.0;
     SPH_HIP(hipMemcpyAsync(&Uh, info + kWiU, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     SPH_HIP(hipStreamSynchronize(ctx->stream));

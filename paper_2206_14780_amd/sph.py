@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sph.h")
 
 SPH_OK, SPH_STALLED, SPH_NOT_CONVERGED = 0, 1, 2
 SPH_E_ARG, SPH_E_OOM, SPH_E_HIP, SPH_E_OVERFLOW, SPH_E_NONFINITE = -1, -2, -3, -4, -5
-SPH_F64, SPH_F32 = 0, 1
+SPH_F64, SPH_F32, SPH_MIXED = 0, 1, 2
 SPH_WALL_DYNAMIC, SPH_WALL_DUMMY = 0, 1
 SPH_AVG_ARITH, SPH_AVG_HARMONIC = 0, 1
 SPH_ROBUST, SPH_STANDARD = 0, 1
@@ -365,6 +365,6 @@ def device_particles(w, device: int = 0) -> Particles:
 def device_vec3(a, prec: int, device: int = 0):
     """(n, 3) array -> three contiguous cuda tensors of the precision."""
     import torch
-    dt = torch.float64 if prec == SPH_F64 else torch.float32
+    dt = torch.float32 if prec == SPH_F32 else torch.float64
     dev = torch.device("cuda", device)
     return [torch.as_tensor(a[:, c]).to(dtype=dt).contiguous().to(dev) for c in range(3)]

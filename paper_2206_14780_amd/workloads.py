@@ -106,9 +106,13 @@ def smooth_field(pos, length, rng, n_modes=16, chunk=1 << 21):
     phase = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
     amp = rng.uniform(0.5, 1.0, size=n_modes)
     out = np.empty(pos.shape[0], dtype=np.float64)
+    # the plane-wave sum in FP64 on the CPU; torch's elementwise cos runs on
+    # all host cores (numpy's on one)
+    import torch
+    kt, pt_, at = (torch.from_numpy(np.ascontiguousarray(a)) for a in (kvec.T, phase, amp))
     for s in range(0, pos.shape[0], chunk):
-        p = pos[s:s + chunk]
-        out[s:s + chunk] = np.cos(p @ kvec.T + phase[None, :]) @ amp
+        p = torch.from_numpy(np.ascontiguousarray(pos[s:s + chunk]))
+        out[s:s + chunk] = (torch.cos(p @ kt + pt_[None, :]) @ at).numpy()
     lo, hi = out.min(), out.max()
     return (out - lo) / (hi - lo) if hi > lo else np.zeros_like(out)
 

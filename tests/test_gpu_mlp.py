@@ -237,7 +237,7 @@ def _solve_pair(ctx, w, prec, p, X0, tol):
 def test_solve_with_learned_start_fp64(ctx, x0_given):
     w = small_tank(seed=12, tol=1e-12)
     w.rhs[w.ptype != W.FLUID] = 0.0
-    p = WS.fixed_blend_params([0.0, 1.0, 1.0])  # the first-order Neumann start
+    p = WS.fixed_blend_params([0.0, 1.0, 1.0])  # one Jacobi sweep from u
     X0 = w.rhs.copy() if x0_given else None
     Xg, rep, x0, use, rr_l, rr_p, ops = _solve_pair(ctx, w, S.SPH_F64, p, X0, 1e-12)
     assert rep["status"] == S.SPH_OK
@@ -273,3 +273,26 @@ def test_solve_with_learned_start_fp32(ctx, wall):
     assert rep["status"] == S.SPH_OK
     Xo, _, _ = O.solve(ops, w.rhs, X0=x0, tol=1e-12, max_iter=2000)
     assert rel_l2(Xg, Xo) < 1e-5
+
+
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+def test_solve_with_learned_start_mixed(ctx, op_mode):
+    # FP32 operator, FP64 solution: the learned start (computed with the FP32
+    # operator) enters the FP64 solution vector
+    w = small_tank(seed=15, tol=1e-6)
+    w.rhs[w.ptype != W.FLUID] = 0.0
+    p = WS.fixed_blend_params([0.0, 1.0, 1.0])
+    case = GpuCase(ctx, w)
+    Xg, rep = case.solve(w.rhs, S.SPH_MIXED, X0=w.rhs.copy(), tol=1e-6, op_mode=op_mode,
+                         warm_params=_cuda(p), warm_u=S.device_vec3(w.rhs, S.SPH_MIXED))
+    assert rep["status"] == S.SPH_OK
+    ops = O.Operator.from_workload(w, jacobi=True)
+    Xo, _, _ = O.solve(ops, w.rhs, tol=1e-12, max_iter=2000)
+    assert rel_l2(Xg, Xo) < 1e-5
+    opu = O.Operator.from_workload(w, jacobi=False)
+    So, Uo = WS.samples(opu, w.rhs, w.rhs, w.mu, w.rho, w.ptype)
+    xl = WS.learned_start(opu, p, So, Uo, w.rhs, w.ptype)
+    _, use, rr_l, rr_p = WS.select(ops, w.rhs, w.rhs, xl)
+    assert rep["warm_used"] == [int(v) for v in use]
+    assert np.allclose(rep["plain_rr"], rr_p, rtol=1e-9)
+    assert np.allclose(rep["warm_rr"], rr_l, rtol=1e-3)

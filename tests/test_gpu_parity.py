@@ -146,6 +146,40 @@ def test_solve_fp32_ragged_tank(ctx, op_mode, seed, wall):
         assert rep["true_rr"][c] < rep["tau2"][c] * 1.0001 or rep["bb"][c] == 0.0
 
 
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+@pytest.mark.parametrize("seed,wall", [(21, W.WALL_DUMMY), (22, W.WALL_DYNAMIC)])
+def test_solve_mixed_ragged_tank(ctx, op_mode, seed, wall):
+    # FP32 operator and Krylov vectors, FP64 solution and caller arrays
+    w = small_tank(seed=seed, wall=wall)
+    print(f"[solve-mixed] {w.name} seed={seed} mode={op_mode}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_MIXED, tol=1e-6, op_mode=op_mode)
+    Xo, ro, _ = O.solve(oracle_op(w), w.rhs, tol=1e-12)
+    assert rep["status"] == S.SPH_OK
+    assert rel_l2(X, Xo) < 1e-5
+    for c in range(3):
+        assert rep["true_rr"][c] < rep["tau2"][c] or rep["bb"][c] == 0.0
+
+
+def test_mixed_reaches_tolerances_fp32_storage_cannot(ctx):
+    # Stiff rows with a smooth solution: rounding x to FP32 leaves a scaled
+    # residual of about 2^-24 A_rr |x| / |b| (a mode of eigenvalue lam of
+    # dt L has x = b / (1 + lam) and A_rr >> 1 + lam), here far above 1e-7;
+    # with the solution accumulated in FP64 the FP32 operator reaches it.
+    w = W.warmstart_box(20, seed=4003, tol=1e-7)
+    g = GpuCase(ctx, w)
+    print("[stiff] fp32 / mixed", flush=True)
+    X32, r32 = g.solve(w.rhs, S.SPH_F32, tol=1e-7, max_iter=2000)
+    Xm, rm = g.solve(w.rhs, S.SPH_MIXED, tol=1e-7, max_iter=2000)
+    Xo, _, _ = O.solve(oracle_op(w), w.rhs, tol=1e-13)
+    assert rm["status"] == S.SPH_OK
+    assert all(rm["true_rr"][c] < rm["tau2"][c] for c in range(3))
+    assert r32["status"] in (S.SPH_STALLED, S.SPH_NOT_CONVERGED)
+    assert any(r32["true_rr"][c] >= r32["tau2"][c] for c in range(3))
+    # solution error <= cond(D^-1 A) * relative residual, cond ~ 2 A_rr here
+    assert rel_l2(Xm, Xo) < 2e-3
+
+
 def test_solve_fp64_ragged_tank_both_variants(ctx):
     w = small_tank(seed=31)
     g = GpuCase(ctx, w)

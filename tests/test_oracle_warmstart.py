@@ -1,8 +1,9 @@
 """Pins of the warm-start oracle (features, learned start, fallback) against
 what linear algebra fixes: fixed blends reproduce b and u exactly, the
 increment u - A u vanishes on constant fields (rows of A sum to one), the
-blend u + (u - A u) is the first-order Neumann approximation of
-(I + dt L)^-1 u (error O(dt^2) where u alone is O(dt)), dummy wall rows are
+blend u + D^-1 (u - A u) is one Jacobi sweep from u (error against
+(I + dt L)^-1 u of second order in dt where u alone errs to first order),
+the Jacobi blend on a single-site system is exact, dummy wall rows are
 satisfied exactly, and the fallback keeps the smaller true residual."""
 import numpy as np
 import pytest
@@ -70,10 +71,11 @@ def test_scalar_features_are_the_workload_parameters():
     assert np.allclose(S[fl, 3], np.log10(37.0 / 1.3 ** 2), rtol=0, atol=1e-14)
 
 
-def test_neumann_blend_is_second_order_in_dt():
-    # x* = (I + dt L)^-1 u: the start u errs by O(dt), u + (u - A u) =
-    # (I - dt L) u by O(dt^2).  Halving dt must halve the first error and
-    # quarter the second (periodic fluid, no walls, so A = I + dt L exactly).
+def test_jacobi_blend_is_second_order_in_dt():
+    # x* = (I + dt L)^-1 u: the start u errs by O(dt); u + D^-1 (u - A u)
+    # = u - D^-1 dt L u with D = 1 + O(dt) errs by O(dt^2).  Halving dt must
+    # halve the first error and quarter the second (periodic fluid, no walls,
+    # so A = I + dt L exactly).
     rng = np.random.default_rng(3)
     pos, pt = W.lattice((6, 6, 6), 1.0, jitter=0.15, rng=rng)
     N = pos.shape[0]
@@ -123,3 +125,18 @@ def test_fallback_keeps_the_smaller_residual(wall):
     assert rr_l[0] < 1e-20 and rr_l[2] < 1e-20
     assert np.array_equal(x0[:, 1], u[:, 1])
     assert np.array_equal(x0[:, 0], bad[:, 0])
+
+
+@pytest.mark.parametrize("wall", [W.WALL_DYNAMIC, W.WALL_DUMMY])
+def test_blend_011_is_one_jacobi_sweep(wall):
+    # with b = u the blend o = (0, 1, 1) is x0 = u + D^-1 (b - A u) on fluid
+    # rows: one Jacobi sweep from u, checked against the dense matrix
+    kw, pt, u, _ = _case(wall=wall, dt_nu=150.0)
+    op = O.Operator(jacobi=False, **kw)
+    A = op.dense()
+    fl = pt == W.FLUID
+    S, U = WS.samples(op, u, u, kw["mu"], kw["rho"], pt)
+    x0 = WS.learned_start(op, WS.fixed_blend_params([0, 1, 1]), S, U, u, pt)
+    jac = u + (u - A @ u) / np.diag(A)[:, None]
+    assert np.allclose(x0[fl], jac[fl], rtol=1e-6, atol=1e-6 * np.abs(jac).max())
+    assert np.abs(np.diag(A)[fl]).min() > 10.0  # a stiff case: D matters
