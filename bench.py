@@ -10,8 +10,11 @@ HBM: neighbour build by counting sort, cached operator build, and the solve.
 Prints one JSON line: particle-iterations per second of the whole step, the
 roofline of the dominant kernel (the operator launch that computes A r_star
 with its dot products, timed with HIP events on the library's stream over the
-timed region), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+timed region), the FP64 CPU oracle timed on a bounded sample of the same
+workload, and the plain-versus-learned comparison: on held-out 160^3 boxes
+(4,491,628 particles) of the learned start's workload family, the time to a
+1e-6 relative residual of the plain previous-step start with the FP64
+operator against the learned start with the FP32 operator (FP64 solution).
 """
 import argparse
 import json
@@ -57,6 +60,10 @@ def parse():
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-sample-iters", type=int, default=4,
                     help="BiCGSTAB iterations of the oracle's timed sample (0 = skip)")
+    ap.add_argument("--learned-n", type=int, default=160,
+                    help="fluid particles per side of the plain-vs-learned boxes (0 = skip)")
+    ap.add_argument("--learned-seeds", type=int, default=3, help="held-out boxes compared")
+    ap.add_argument("--learned-reps", type=int, default=2, help="timed solves per box and start")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device once "
                          "(a kernel of known traffic to scale hardware byte counters)")
@@ -83,6 +90,53 @@ def cpu_baseline(w, sample_iters):
         "sample": (f"full {w.n}-particle tank, FP64 robust BiCGSTAB, first {iters} iterations "
                    f"({t_solve:.1f} s; neighbour grid {t_nbr:.1f} s not counted)"),
     }
+
+
+def plain_vs_learned(ctx, n, seeds, reps):
+    """Time to tolerance of plain and learned starts on held-out boxes."""
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import warmstart as WS
+    from paper_2206_14780_amd import workloads as W
+
+    params = torch.as_tensor(WS.load()).cuda()
+    legs = (("plain_f64", S.SPH_F64, None), ("plain_f32op", S.SPH_MIXED, None),
+            ("learned_f32op", S.SPH_MIXED, params))
+    rows = []
+    for seed in range(4500, 4500 + seeds):
+        w = W.warmstart_box(n, seed=seed, tol=1e-6)
+        r = WS.Resident(ctx, w)
+        row = {"seed": seed, "dt_nu_dp2": round(w.meta["dt_nu_dp2"], 2), "nu": round(w.meta["nu"], 3)}
+        for name, prec, warm in legs:
+            r.solve(prec, 1e-6, warm_params=warm)  # warm-up
+            wall, dev = [], []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, rep = r.solve(prec, 1e-6, warm_params=warm)
+                wall.append((time.perf_counter() - t0) * 1e3)
+                dev.append(rep["setup_ms"] + rep["iterate_ms"])
+                assert rep["status"] == S.SPH_OK, (name, rep["status"])
+            row[name] = {"ms": round(float(np.median(wall)), 2),
+                         "device_ms": round(float(np.median(dev)), 2), "iters": rep["iters"],
+                         "true_rel_res": round(max(float(np.sqrt(t / b)) for t, b in
+                                                   zip(rep["true_rr"], rep["bb"]) if b > 0), 9)}
+            if warm is not None:
+                row[name]["warm_ms"] = round(rep["warm_ms"], 3)
+                row[name]["warm_used"] = rep["warm_used"]
+        row["speedup"] = round(row["plain_f64"]["ms"] / row["learned_f32op"]["ms"], 3)
+        rows.append(row)
+        print(f"[bench] learned box seed {seed}: {json.dumps(row)}", flush=True)
+        del r
+    return {"workload": f"open-top box {n}^3 jittered fluid + 3 wall layers (dummy), "
+                        f"N={w.n}, held-out seeds {4500}..{4500 + seeds - 1}, b = u, x0 = u, tol 1e-6",
+            "baseline": "plain previous-step start, FP64 operator and vectors",
+            "learned": "learned start (BF16-MFMA MLP) + FP32 operator/Krylov vectors, FP64 solution",
+            "speedup_median": round(float(np.median([r["speedup"] for r in rows])), 3),
+            "speedup_min": round(float(np.min([r["speedup"] for r in rows])), 3),
+            "boxes": rows}
 
 
 def main():
@@ -163,6 +217,11 @@ def main():
                     "avg_launch_ms": round(a_ms, 4), "alg_bytes_per_launch": int(alg_bytes),
                     "mat_nnz": int(nnz), "mat_slots": int(slots)}
 
+    pvl = None
+    if args.learned_n > 0 and args.learned_seeds > 0:
+        print("[bench] plain vs learned", flush=True)
+        pvl = plain_vs_learned(ctx, args.learned_n, args.learned_seeds, args.learned_reps)
+
     cpu = None
     if args.cpu_sample_iters > 0:
         print("[bench] cpu baseline (oracle)", flush=True)
@@ -192,6 +251,7 @@ def main():
                          for t, b in zip(reps[-1]["true_rr"], reps[-1]["bb"])],
         "launches_per_solve": reps[-1]["launches"],
         "roofline": roofline,
+        "plain_vs_learned": pvl,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

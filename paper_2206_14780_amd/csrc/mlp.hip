@@ -30,6 +30,15 @@ constexpr int kWaves = 4;             // waves per block
 constexpr int kThreads = kWaves * kWave;
 constexpr int kPad = 65;              // padded row of the per-wave transpose tile
 
+// Orders a wave's own LDS writes before its later LDS reads by other lanes
+// (every tile and output staging area belongs to one wave, so waves of a
+// block never wait for each other after the parameters are loaded).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline uint16_t f2bf(float f) {  // nearest, ties to even (finite inputs)
     uint32_t u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);
@@ -93,10 +102,10 @@ __device__ inline bf16x4 bfrag_bwd(const uint16_t* __restrict__ w, int s, int t,
 __device__ inline void d_to_a(float* tile, const float (&v)[4][4], bf16x4 (&a)[4], int g, int c) {
     for (int t = 0; t < 4; ++t)
         for (int r = 0; r < 4; ++r) tile[(4 * g + r) * kPad + 16 * t + c] = v[t][r];
-    __syncthreads();
+    wave_sync();
     for (int s = 0; s < 4; ++s)
         for (int r = 0; r < 4; ++r) a[s][r] = (short)f2bf(tile[c * kPad + 16 * s + 4 * g + r]);
-    __syncthreads();
+    wave_sync();
 }
 
 // One 64x64 product on MFMA: out[t] (D layout) = A (16x64) x Wfrag.
@@ -150,7 +159,7 @@ __device__ inline void tile_forward(Smem& sm, Tile& T, int wave, int g, int c) {
     // layer 4 on the vector ALU: h3 through the LDS tile
     for (int t = 0; t < 4; ++t)
         for (int r = 0; r < 4; ++r) tile[(4 * g + r) * kPad + 16 * t + c] = T.h3[t][r];
-    __syncthreads();
+    wave_sync();
     const int lane = threadIdx.x % kWave;
     if (lane < 16 * kOut) {
         const int row = lane / kOut, k = lane % kOut;
@@ -158,7 +167,7 @@ __device__ inline void tile_forward(Smem& sm, Tile& T, int wave, int g, int c) {
         for (int col = 0; col < kH; ++col) o = __builtin_fmaf(tile[row * kPad + col], sm.w4[col * kOut + k], o);
         sm.go[wave][row * 4 + k] = o;
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Loads sample `s` (or zeros when s < 0) into the lane's tile rows.
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_forward(const float* __restric
             w[2] = o[2];
             w[3] = pred;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
             }
             for (int j = 0; j < 3; ++j) sm.go[wave][lane * 4 + j] = go[j];
         }
-        __syncthreads();
+        wave_sync();
         const float* GO = sm.go[wave];
         // layer 4: dW4[col][k] += sum_row h3[row][col] g_o[row][k] (h3 still in the tile)
         for (int row = 0; row < 16; ++row) {
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
                 d = __builtin_fmaf(GO[row * 4 + 2], sm.w4[col * kOut + 2], d);
                 dz[t][r] = T.h3[t][r] > 0.f ? d : 0.f;
             }
-        __syncthreads();
+        wave_sync();
         // layer 3: weight gradient h2^T dz3, bias gradient, data gradient dz3 W3^T
         for (int t = 0; t < 4; ++t)
             for (int r = 0; r < 4; ++r) gb3[t] += dz[t][r];

@@ -45,25 +45,37 @@ struct WarmOp {
     const double* diag64;   // D = A_rr
 };
 
+// Optional output of the feature pass (cached operator only): the residual
+// b64 - A u of the start x0 = u (T, cell order AoS) and 3 partials of its
+// r.r per block of the pass (kWarmFeatBlocks at most).
+template <typename T>
+struct PlainResidual {
+    const double* b64;
+    T* r;
+    double* part;
+};
+constexpr int kWarmFeatBlocks = 2048;
+
 // U and the samples of every row: orig_order = 1 writes sample 3 perm[r] + c
 // (caller order), 0 writes 3 r + c (cell order).  rhs: caller order, of the
 // caller's precision C; u: cell order, AoS; tgt: caller order FP64 or null.
 // info: kWiSize doubles.
 template <typename T, typename C>
-sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
-                        const double* const tgt[3], int32_t orig_order, float* samples, double* info);
+sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const C* u,
+                        const double* const tgt[3], int32_t orig_order, float* samples, double* info,
+                        const PlainResidual<T>* pr);
 // Partials (3 per block, nblk blocks) of b64 . b64 (true r.r of the zero start).
 sph_status warm_zero_rr(sph_ctx* ctx, int64_t n, int32_t nblk, const double* b64, double* part);
 // Per-component choice between the learned start (xl, residual rl) and the
 // plain start (x, residual r0 if plain_given, else b) by their true r.r
 // partials pl, pp (3 per part); x and r0 receive the chosen start.
 template <typename T, typename X>
-sph_status warm_select(sph_ctx* ctx, int64_t n, int32_t grid, int32_t block, const double* pl, const double* pp,
-                       int32_t nparts, int32_t plain_given, X* x, const T* xl, const T* rl, const T* b, T* r0,
-                       double* info);
+sph_status warm_select(sph_ctx* ctx, int64_t n, int32_t grid, int32_t block, const double* pl, int32_t nl,
+                       const double* pp, int32_t np, int32_t plain_given, X* x, const T* xl, const T* rl,
+                       const T* b, T* r0, double* info);
 // The learned guess (cell order, AoS) into x; rhs of the caller's precision C.
 template <typename T, typename C>
-sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
-                        const float* params, T* x, double* info);
+sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const C* u,
+                        const float* params, T* x, double* info, const PlainResidual<T>* pr);
 
 }  // namespace sph

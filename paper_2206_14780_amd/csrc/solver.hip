@@ -647,7 +647,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
 
     S.sc.tol2 = o->tol * o->tol;
     const bool vec32 = sizeof(T) == 4;
-    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : (vec32 ? 1e-6 : 0.0);
+    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : 0.1;
     S.sc.tr_blocks = L.grid_apply;
     S.sc.floor_ = o->floor >= 0.0 ? o->floor : (vec32 ? (double)FLT_MIN : DBL_MIN);
     S.sc.max_iter = o->max_iter;
@@ -669,26 +669,43 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         // start (x, its residual in tmp), per component by true r.r
         SPH_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
         SPH_TRY(ctx->ensure_t(kWarmInfo, kWiSize, &winfo));
-        const void* uu[3];
-        for (int c = 0; c < 3; ++c) uu[c] = o->warm_u[c] ? o->warm_u[c] : rhs[c];
-        if constexpr (sizeof(X) == sizeof(T))
-            SPH_TRY(gather_vec3<T>(ctx, nb, uu, S.p));
-        else
-            SPH_TRY((gather_vec3_cvt<X, T>(ctx, nb, uu, S.p)));
-        const WarmOp<T> w{nb, S.pv, S.op, S.mode, &S.sell, S.diag64};
-        SPH_TRY((warm_learned<T, X>(ctx, w, rhs, S.p, o->warm_params, S.s, winfo)));
+        // u: warm_u, or per null component the initial guess (x0_given) or
+        // b.  When u is the plain start itself and the matrix is cached, the
+        // feature pass also yields the plain start's residual.
+        const bool u_is_x0 = o->x0_given && !o->warm_u[0] && !o->warm_u[1] && !o->warm_u[2];
+        const bool fuse = u_is_x0 && S.mode == SPH_OP_CACHED;
+        if (o->x0_given) SPH_TRY(gather_vec3<X>(ctx, nb, (const void* const*)xout, S.x));
+        const X* ucell = S.x;
+        if (!u_is_x0) {
+            const void* uu[3];
+            for (int c = 0; c < 3; ++c) uu[c] = o->warm_u[c] ? o->warm_u[c] : (o->x0_given ? xout[c] : rhs[c]);
+            X* ub = nullptr;
+            SPH_TRY(ctx->ensure_t(kWarmU, v3, &ub));
+            SPH_TRY(gather_vec3<X>(ctx, nb, uu, ub));
+            ucell = ub;
+        }
         double* pl = S.pchk;
         double* pp = S.pchk + 3 * (size_t)L.grid_apply;
-        S.template apply<kDotResid, T>(nullptr, S.s, S.as, nullptr, pl);
-        if (o->x0_given) {
-            SPH_TRY(gather_vec3<X>(ctx, nb, (const void* const*)xout, S.x));
-            S.template apply<kDotResid, X>(nullptr, S.x, S.tmp, nullptr, pp);
-        } else {
-            SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
-            SPH_TRY(warm_zero_rr(ctx, n, L.grid_apply, S.b64, pp));
+        int32_t np = L.grid_apply;
+        PlainResidual<T> pr{S.b64, S.tmp, nullptr};
+        if (fuse) {
+            SPH_TRY(ctx->ensure_t(kWarmPart2, 3 * (size_t)kWarmFeatBlocks, &pp));
+            pr.part = pp;
+            np = (int32_t)std::min<int64_t>(ceil_div(n, kBlock), kWarmFeatBlocks);
         }
-        SPH_TRY((warm_select<T, X>(ctx, n, L.grid_stream, L.block_stream, pl, pp, L.grid_apply, o->x0_given, S.x,
-                                   S.s, S.as, S.b, S.tmp, winfo)));
+        const WarmOp<T> w{nb, S.pv, S.op, S.mode, &S.sell, S.diag64};
+        SPH_TRY((warm_learned<T, X>(ctx, w, rhs, ucell, o->warm_params, S.s, winfo, fuse ? &pr : nullptr)));
+        S.template apply<kDotResid, T>(nullptr, S.s, S.as, nullptr, pl);
+        if (!fuse) {
+            if (o->x0_given) {
+                S.template apply<kDotResid, X>(nullptr, S.x, S.tmp, nullptr, pp);
+            } else {
+                SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
+                SPH_TRY(warm_zero_rr(ctx, n, L.grid_apply, S.b64, pp));
+            }
+        }
+        SPH_TRY((warm_select<T, X>(ctx, n, L.grid_stream, L.block_stream, pl, L.grid_apply, pp, np, o->x0_given,
+                                   S.x, S.s, S.as, S.b, S.tmp, winfo)));
         r0 = S.tmp;
         S.launches += 11;
         SPH_HIP(hipEventRecord(ctx->ev[6], ctx->stream));

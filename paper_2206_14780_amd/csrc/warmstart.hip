@@ -23,6 +23,7 @@ using mlp::kSample;
 namespace {
 
 constexpr int kStatBlocks = 256;
+constexpr unsigned kFeatBlocks = kWarmFeatBlocks;  // grid of the cached-operator feature kernel
 
 template <typename C>
 struct Rhs {
@@ -61,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_warm_scale(const double* __restrict_
 }
 
 // Writes the 3 samples of row r given d.
-template <typename T, typename C>
-__device__ inline void warm_write(int64_t r, const Rhs<C>& rhs, const V3<T>& u, const double (&d)[3],
+template <typename C>
+__device__ inline void warm_write(int64_t r, const Rhs<C>& rhs, const V3<C>& u, const double (&d)[3],
                                   const PartView& pv, double dt, double h, double U,
                                   const double* const* tgt, float* __restrict__ out) {
     const double nu = pv.mu[r] / pv.rho[r];
@@ -87,7 +88,7 @@ template <typename T, typename C>
 struct FeatArgs {
     int64_t n;
     Rhs<C> rhs;
-    const T* u;              // cell order, AoS
+    const C* u;              // cell order, AoS, caller precision
     PartView pv;
     double dt, h;
     const double* diag64;    // D = A_rr
@@ -97,6 +98,11 @@ struct FeatArgs {
     int32_t has_tgt;
     int32_t orig_order;
     float* samples;
+    // optional (cached operator): the FP64-accurate residual b64 - A u of the
+    // start x0 = u, rounded to T, and per-block partials of its r.r
+    const double* b64;
+    T* rplain;
+    double* part;
 };
 
 template <typename T, typename C>
@@ -110,28 +116,45 @@ __device__ inline void zero_row(float* o) {
 }
 
 // Cached matrix: d = -sum_k c_k (u_k - u_r) with c = A_rk / D (Jacobi
-// scaled), or -(1/D) sum_k c_k (u_k - u_r) with c = A_rk.
+// scaled), or -(1/D) sum_k c_k (u_k - u_r) with c = A_rk.  The same FP64
+// sum gives the residual of x0 = u, b - (rs u + sum_k c_k (u_k - u_r)), on
+// every row when a.rplain is set (grid-stride, fixed grid).
 template <typename T, typename C>
 __global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T, C> a, Sell<T> A) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.n) return;
-    float* o = sample_row(a, r);
-    if (a.pv.type[r] != SPH_FLUID) {
-        zero_row(o);
-        return;
+    __shared__ double lds[3 * kMaxWaves];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        float* o = sample_row(a, r);
+        const bool fluid = a.pv.type[r] == SPH_FLUID;
+        if (!fluid) zero_row(o);
+        if (!fluid && !a.rplain) continue;
+        const int64_t s = r / kWave;
+        const int64_t base = A.sl_ptr[s] + (r % kWave);
+        const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
+        const V3<C> us = ld3(a.u, r);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        sell_row<T, true, double, C>(A, base, width, (int32_t)r, a.u, us, s0, s1, s2);
+        if (a.rplain) {
+            const double rs = A.rs64[r];
+            const V3<double> bb = ld3(a.b64, r);
+            const double q0 = bb.x - (rs * (double)us.x + s0);
+            const double q1 = bb.y - (rs * (double)us.y + s1);
+            const double q2 = bb.z - (rs * (double)us.z + s2);
+            acc[0] += q0 * q0;
+            acc[1] += q1 * q1;
+            acc[2] += q2 * q2;
+            st3(a.rplain, r, V3<T>{(T)q0, (T)q1, (T)q2});
+        }
+        if (!fluid) continue;
+        double d[3] = {-s0, -s1, -s2};
+        if (!a.jacobi) {
+            const double D = a.diag64[r];
+            for (int c = 0; c < 3; ++c) d[c] /= D;
+        }
+        warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
     }
-    const int64_t s = r / kWave;
-    const int64_t base = A.sl_ptr[s] + (r % kWave);
-    const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
-    const V3<T> us = ld3(a.u, r);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    sell_row<T, true>(A, base, width, (int32_t)r, a.u, us, s0, s1, s2);
-    double d[3] = {-s0, -s1, -s2};
-    if (!a.jacobi) {
-        const double D = a.diag64[r];
-        for (int c = 0; c < 3; ++c) d[c] /= D;
-    }
-    warm_write<T, C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+    if (a.rplain) write_partials<3>(acc, lds, a.part);
 }
 
 // On-the-fly operator: d = dt sum_a w_ra (u_a - u_r) / D.
@@ -144,18 +167,18 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_otf(FeatArgs<T, C> a, NbrV
         zero_row(o);
         return;
     }
-    const V3<T> us = ld3(a.u, r);
+    const V3<C> us = ld3(a.u, r);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for_each_neighbor(nv, (int32_t)r, [&](int32_t k, double r2) {
         const double w = pair_w(a.pv, nv.g, avg, (int32_t)r, k, r2);
-        const V3<T> uk = ld3(a.u, k);
+        const V3<C> uk = ld3(a.u, k);
         s0 += w * ((double)uk.x - (double)us.x);
         s1 += w * ((double)uk.y - (double)us.y);
         s2 += w * ((double)uk.z - (double)us.z);
     });
     const double f = a.dt / a.diag64[r];
     const double d[3] = {f * s0, f * s1, f * s2};
-    warm_write<T, C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+    warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
 }
 
 // x = U pred on fluid rows, b on dynamic walls, 0 on dummy walls (filled next).
@@ -221,7 +244,8 @@ template <typename T, typename C>
 sph_status launch_features(sph_ctx* ctx, const WarmOp<T>& w, const FeatArgs<T, C>& a) {
     const unsigned grid = (unsigned)ceil_div(a.n, kBlock);
     if (w.mode == SPH_OP_CACHED)
-        hipLaunchKernelGGL((k_warm_feat_sell<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, a, *w.sell);
+        hipLaunchKernelGGL((k_warm_feat_sell<T, C>), dim3(std::min<unsigned>(grid, kFeatBlocks)), dim3(kBlock), 0,
+                           ctx->stream, a, *w.sell);
     else
         hipLaunchKernelGGL((k_warm_feat_otf<T, C>), dim3(grid), dim3(kBlock), 0, ctx->stream, a, w.nb->view(),
                            w.op.avg);
@@ -258,16 +282,16 @@ __global__ __launch_bounds__(kBlock) void k_warm_bb(int64_t n, const double* __r
 // given) or b (zero start).  Every block reduces both sets of partials in
 // the same fixed order, so all blocks take the same decision.
 template <typename T, typename X>
-__global__ __launch_bounds__(kMaxBlock) void k_warm_select(int64_t n, const double* __restrict__ pl,
-                                                           const double* __restrict__ pp, int nparts,
+__global__ __launch_bounds__(kMaxBlock) void k_warm_select(int64_t n, const double* __restrict__ pl, int nl,
+                                                           const double* __restrict__ pp, int np,
                                                            int32_t plain_given, X* __restrict__ x,
                                                            const T* __restrict__ xl, const T* __restrict__ rl,
                                                            const T* __restrict__ b, T* __restrict__ r0,
                                                            double* __restrict__ info) {
     __shared__ double lds[3 * kMaxWaves];
     double rrl[3], rrp[3];
-    reduce_partials<3>(pl, nparts, rrl, lds);
-    reduce_partials<3>(pp, nparts, rrp, lds);
+    reduce_partials<3>(pl, nl, rrl, lds);
+    reduce_partials<3>(pp, np, rrp, lds);
     bool use[3];
     for (int c = 0; c < 3; ++c) use[c] = rrl[c] < rrp[c];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -298,26 +322,28 @@ sph_status warm_zero_rr(sph_ctx* ctx, int64_t n, int32_t nblk, const double* b64
 }
 
 template <typename T, typename X>
-sph_status warm_select(sph_ctx* ctx, int64_t n, int32_t grid, int32_t block, const double* pl, const double* pp,
-                       int32_t nparts, int32_t plain_given, X* x, const T* xl, const T* rl, const T* b, T* r0,
-                       double* info) {
-    hipLaunchKernelGGL((k_warm_select<T, X>), dim3(grid), dim3(block), 0, ctx->stream, n, pl, pp, nparts,
+sph_status warm_select(sph_ctx* ctx, int64_t n, int32_t grid, int32_t block, const double* pl, int32_t nl,
+                       const double* pp, int32_t np, int32_t plain_given, X* x, const T* xl, const T* rl,
+                       const T* b, T* r0, double* info) {
+    hipLaunchKernelGGL((k_warm_select<T, X>), dim3(grid), dim3(block), 0, ctx->stream, n, pl, nl, pp, np,
                        plain_given, x, xl, rl, b, r0, info);
     SPH_LAUNCHED("k_warm_select");
     return SPH_OK;
 }
 
 #define SPH_WARM_SELECT(T, X)                                                                                   \
-    template sph_status warm_select<T, X>(sph_ctx*, int64_t, int32_t, int32_t, const double*, const double*,     \
-                                          int32_t, int32_t, X*, const T*, const T*, const T*, T*, double*);
+    template sph_status warm_select<T, X>(sph_ctx*, int64_t, int32_t, int32_t, const double*, int32_t,          \
+                                          const double*, int32_t, int32_t, X*, const T*, const T*, const T*, T*,   \
+                                          double*);
 SPH_WARM_SELECT(float, float)
 SPH_WARM_SELECT(double, double)
 SPH_WARM_SELECT(float, double)
 #undef SPH_WARM_SELECT
 
 template <typename T, typename C>
-sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
-                        const double* const tgt[3], int32_t orig_order, float* samples, double* info) {
+sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const C* u,
+                        const double* const tgt[3], int32_t orig_order, float* samples, double* info,
+                        const PlainResidual<T>* pr) {
     const int64_t n = w.nb->n;
     double* part = nullptr;
     SPH_TRY(ctx->ensure_t(kWarmPart, 2 * kStatBlocks, &part));
@@ -340,17 +366,20 @@ sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[
     for (int c = 0; c < 3; ++c) a.tgt[c] = tgt ? tgt[c] : nullptr;
     a.orig_order = orig_order;
     a.samples = samples;
+    a.b64 = pr ? pr->b64 : nullptr;
+    a.rplain = pr ? pr->r : nullptr;
+    a.part = pr ? pr->part : nullptr;
     return launch_features<T, C>(ctx, w, a);
 }
 
 template <typename T, typename C>
-sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const T* u,
-                        const float* params, T* x, double* info) {
+sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[3], const C* u,
+                        const float* params, T* x, double* info, const PlainResidual<T>* pr) {
     const int64_t n = w.nb->n;
     float *S = nullptr, *O = nullptr;
     SPH_TRY(ctx->ensure_t(kWarmS, (size_t)n * 3 * kSample, &S));
     SPH_TRY(ctx->ensure_t(kWarmO, (size_t)n * 3 * 4, &O));
-    SPH_TRY((warm_samples<T, C>(ctx, w, rhs, u, nullptr, 0, S, info)));
+    SPH_TRY((warm_samples<T, C>(ctx, w, rhs, u, nullptr, 0, S, info, pr)));
     SPH_TRY(mlp::forward(ctx, S, n * 3, params, O));
     const Rhs<C> rb = make_rhs<C>(w.nb, rhs);
     const unsigned grid = (unsigned)ceil_div(n, kBlock);
@@ -369,10 +398,11 @@ sph_status warm_learned(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[
 }
 
 #define SPH_WARM_INST(T, C)                                                                                    \
-    template sph_status warm_samples<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const T*,           \
-                                           const double* const[3], int32_t, float*, double*);                    \
-    template sph_status warm_learned<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const T*,           \
-                                           const float*, T*, double*);
+    template sph_status warm_samples<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const C*,           \
+                                           const double* const[3], int32_t, float*, double*,                     \
+                                           const PlainResidual<T>*);                                              \
+    template sph_status warm_learned<T, C>(sph_ctx*, const WarmOp<T>&, const void* const[3], const C*,           \
+                                           const float*, T*, double*, const PlainResidual<T>*);
 SPH_WARM_INST(float, float)
 SPH_WARM_INST(double, double)
 SPH_WARM_INST(float, double)
@@ -423,7 +453,7 @@ sph_status warmstart_entry(sph_ctx* ctx, const sph_nbr* nb, const sph_particles*
     SPH_TRY(prepare<T>(ctx, nb, p, v, u, &w, &sell, &ucell, &info));
     T* x = nullptr;
     SPH_TRY(ctx->ensure_t(kApplyOut, (size_t)nb->n * 3, &x));
-    SPH_TRY((warm_learned<T, T>(ctx, w, rhs, ucell, params, x, info)));
+    SPH_TRY((warm_learned<T, T>(ctx, w, rhs, ucell, params, x, info, nullptr)));
     SPH_TRY(scatter_vec3<T>(ctx, nb, x, x0));
     if (U) {
         SPH_HIP(hipMemcpyAsync(U, info + kWiU, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -450,7 +480,8 @@ extern "C" sph_status sph_mlp_samples(sph_ctx* ctx, const sph_nbr* nb, const sph
     double* ucell = nullptr;
     double* info = nullptr;
     SPH_TRY(prepare<double>(ctx, nb, p, params, (const void* const*)u, &w, &sell, &ucell, &info));
-    SPH_TRY((warm_samples<double, double>(ctx, w, (const void* const*)rhs, ucell, target, 1, samples, info)));
+    SPH_TRY((warm_samples<double, double>(ctx, w, (const void* const*)rhs, ucell, target, 1, samples, info,
+                                          nullptr)));
     double Uh = 0.0;
     SPH_HIP(hipMemcpyAsync(&Uh, info + kWiU, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     SPH_HIP(hipStreamSynchronize(ctx->stream));

@@ -170,7 +170,7 @@ def make_params(dt, wall, avg, jacobi=True, op_mode=SPH_OP_CACHED) -> sph_visc_p
     return sph_visc_params(float(dt), int(wall), int(avg), int(bool(jacobi)), int(op_mode))
 
 
-def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res_period=50,
+def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res_period=20,
               x0_given=False, poll_every=0, force_stall=None, profile=False,
               restart_drop=-1.0, warm_params=None, warm_u=None) -> sph_solve_opts:
     """Solver options; warm_params / warm_u are cuda tensors (kept alive by

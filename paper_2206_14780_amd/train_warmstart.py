@@ -84,7 +84,7 @@ def main(argv=None):
                                  ("learned_f32", S.SPH_MIXED, params)):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, rep = r.solve(prec, a.eval_tol, x0=r.u, warm_params=warm)
+            _, rep = r.solve(prec, a.eval_tol, warm_params=warm)
             wall = (time.perf_counter() - t) * 1e3
             rel = [float(np.sqrt(rep["true_rr"][c] / rep["bb"][c])) if rep["bb"][c] > 0 else 0.0
                    for c in range(3)]

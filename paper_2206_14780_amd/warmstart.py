@@ -64,26 +64,44 @@ def load(path: str = DEFAULT_WEIGHTS) -> np.ndarray:
 
 
 class Resident:
-    """One workload on the device: particles, neighbour lists, u and b."""
+    """One workload resident on the device: particles, neighbour lists, and
+    u and b in each precision used (copied once, so solves start from data
+    already in HBM)."""
 
-    def __init__(self, ctx: S.Context, w: W.Workload, prec: int = S.SPH_F64):
+    def __init__(self, ctx: S.Context, w: W.Workload):
         self.ctx, self.w = ctx, w
         self.parts = S.device_particles(w)
         self.nb = ctx.sph_build_neighbors(self.parts, S.make_domain(w.lo, w.hi, w.periodic, w.h))
         self.u = w.x0 if w.x0 is not None else w.rhs
         self.params = S.make_params(w.dt, w.wall, w.avg, True, S.SPH_OP_CACHED)
+        self._dev = {}
 
-    def solve(self, prec: int, tol: float, x0=None, warm_params=None, max_iter: int = 10000):
-        """Solve A V = b from x0 (None: zero); warm_params: cuda tensor or None."""
+    def vectors(self, prec: int):
+        """(b, u, x) device vectors of the precision; x is the solution buffer."""
         import torch
-        rhs = S.device_vec3(self.w.rhs, prec)
-        xs = S.device_vec3(np.zeros((self.w.n, 3)) if x0 is None else x0, prec)
-        ud = S.device_vec3(self.u, prec)
-        o = S.make_opts(tol=tol, max_iter=max_iter, x0_given=x0 is not None,
-                        warm_params=warm_params, warm_u=ud if warm_params is not None else None)
-        rep = self.ctx.sph_visc_solve(self.nb, None, self.parts, self.params, prec, rhs, xs, o)
+        if prec not in self._dev:
+            b = S.device_vec3(self.w.rhs, prec)
+            u = S.device_vec3(self.u, prec)
+            self._dev[prec] = (b, u, [torch.empty_like(t) for t in u])
+        return self._dev[prec]
+
+    def solve(self, prec: int, tol: float, from_u: bool = True, warm_params=None,
+              max_iter: int = 10000):
+        """Solve A V = b from x0 = u (from_u) or zero; warm_params: cuda
+        tensor or None.  Returns (x, report); x is overwritten by the next
+        solve of the same precision."""
+        import torch
+        b, u, x = self.vectors(prec)
+        for xc, uc in zip(x, u):
+            if from_u:
+                xc.copy_(uc)
+        # from_u: u is the initial guess, so warm_u stays null (the library
+        # then takes u from x and saves one operator pass)
+        o = S.make_opts(tol=tol, max_iter=max_iter, x0_given=from_u, warm_params=warm_params,
+                        warm_u=None if from_u or warm_params is None else u)
+        rep = self.ctx.sph_visc_solve(self.nb, None, self.parts, self.params, prec, b, x, o)
         torch.cuda.synchronize()
-        return xs, rep
+        return x, rep
 
 
 def generate(ctx: S.Context, make: Callable[[int], W.Workload], seeds: Iterable[int],
@@ -97,12 +115,12 @@ def generate(ctx: S.Context, make: Callable[[int], W.Workload], seeds: Iterable[
         t0 = time.time()
         w = make(seed)
         r = Resident(ctx, w)
-        xs, rep = r.solve(S.SPH_F64, tol, x0=r.u)
+        xs, rep = r.solve(S.SPH_F64, tol)
         if rep["status"] != S.SPH_OK:
             raise RuntimeError(f"training solve {seed} did not converge: {rep['state']}")
         out = torch.empty((3 * w.n, SAMPLE), dtype=torch.float32, device="cuda")
-        U = ctx.sph_mlp_samples(r.nb, r.parts, r.params, S.device_vec3(r.u, S.SPH_F64),
-                                S.device_vec3(w.rhs, S.SPH_F64), xs, out)
+        b64, u64, _ = r.vectors(S.SPH_F64)
+        U = ctx.sph_mlp_samples(r.nb, r.parts, r.params, u64, b64, xs, out)
         fl = torch.as_tensor(np.repeat(w.ptype == W.FLUID, 3), device="cuda")
         chunks.append(out[fl])
         rec = {k2: float(v) for k2, v in w.meta.items() if isinstance(v, (int, float))}

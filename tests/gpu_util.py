@@ -49,6 +49,10 @@ class GpuCase:
         par = S.make_params(w.dt, w.wall, w.avg, jacobi, op_mode)
         rhs = S.device_vec3(B, prec)
         xs = S.device_vec3(np.zeros((w.n, 3)) if X0 is None else X0, prec)
+        # default: the oracle's policy (check every 50 iterations; FP64 never
+        # restarts on a drop, FP32 vectors restart after a 1e-6 drop)
+        opt.setdefault("true_res_period", 50)
+        opt.setdefault("restart_drop", 0.0 if prec == S.SPH_F64 else 1e-6)
         o = S.make_opts(tol=w.tol if tol is None else tol, x0_given=X0 is not None, **opt)
         rep = self.ctx.sph_visc_solve(self.nb, None, self.parts, par, prec, rhs, xs, o,
                                       history_cap=(o.max_iter + 1) if history else 0)

@@ -296,3 +296,25 @@ def test_solve_with_learned_start_mixed(ctx, op_mode):
     assert rep["warm_used"] == [int(v) for v in use]
     assert np.allclose(rep["plain_rr"], rr_p, rtol=1e-9)
     assert np.allclose(rep["warm_rr"], rr_l, rtol=1e-3)
+
+
+@pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_MIXED])
+def test_start_from_x0_matches_explicit_u(ctx, prec):
+    # warm_u null with x0_given takes u = x0 and forms the plain start's
+    # residual inside the feature pass; it must equal the separate path
+    # (u given explicitly) bit for bit
+    w = small_tank(seed=16, tol=1e-8)
+    w.rhs[w.ptype != W.FLUID] = 0.0
+    p = WS.fixed_blend_params([0.2, 0.8, 0.9])
+    case = GpuCase(ctx, w)
+    X0 = w.rhs * 0.9
+    Xa, ra = case.solve(w.rhs, prec, X0=X0, tol=1e-8, warm_params=_cuda(p))
+    Xb, rb = case.solve(w.rhs, prec, X0=X0, tol=1e-8, warm_params=_cuda(p),
+                        warm_u=S.device_vec3(X0, prec))
+    assert ra["status"] == rb["status"] == S.SPH_OK
+    # the residual vectors are identical; their norms are reduced over two
+    # different grids (last-bit differences only)
+    assert ra["warm_used"] == rb["warm_used"]
+    assert np.allclose(ra["plain_rr"], rb["plain_rr"], rtol=1e-13, atol=0)
+    assert ra["history"] == rb["history"]
+    assert np.array_equal(Xa, Xb)
