@@ -180,16 +180,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_pos(int64_t n, const int32_t*
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ y,
                                                        const double* __restrict__ z,
-                                                       double* __restrict__ px, double* __restrict__ py,
-                                                       double* __restrict__ pz,
+                                                       Pos4* __restrict__ pos,
                                                        int32_t* __restrict__ scell,
                                                        int32_t* __restrict__ iperm) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int32_t o = perm[s];
-    px[s] = x[o];
-    py[s] = y[o];
-    pz[s] = z[o];
+    pos[s] = Pos4{x[o], y[o], z[o], 0.0};
     scell[s] = cell[o];
     iperm[o] = (int32_t)s;
 }
@@ -235,6 +232,9 @@ static sph_status make_grid(sph_ctx* ctx, const sph_domain* dom, Grid* g, int64_
     const double s = 2.0 * dom->h;
     g->h = dom->h;
     g->cut2 = s * s;
+    g->inv_h = 1.0 / dom->h;
+    g->inv_h3 = g->inv_h * g->inv_h * g->inv_h;
+    g->inv_h5 = g->inv_h3 * g->inv_h * g->inv_h;
     int64_t total = 1;
     for (int a = 0; a < 3; ++a) {
         double L = dom->hi[a] - dom->lo[a];
@@ -296,9 +296,7 @@ extern "C" sph_status sph_build_neighbors(sph_ctx* ctx, const sph_particles* p, 
     if (hipMalloc(&nb->scell, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
     if (hipMalloc(&nb->perm, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
     if (hipMalloc(&nb->iperm, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->px, sizeof(double) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->py, sizeof(double) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->pz, sizeof(double) * n) != hipSuccess) return fail_oom();
+    if (hipMalloc(&nb->pos, sizeof(Pos4) * n) != hipSuccess) return fail_oom();
     if (hipMalloc(&cell, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
     if (hipMalloc(&count, sizeof(int32_t) * ncell) != hipSuccess) return fail_oom();
     if (hipMalloc(&fill, sizeof(int32_t) * ncell) != hipSuccess) return fail_oom();
@@ -324,7 +322,7 @@ extern "C" sph_status sph_build_neighbors(sph_ctx* ctx, const sph_particles* p, 
     hipLaunchKernelGGL(k_scatter, dim3(gp), dim3(kBlock), 0, ctx->stream, n, cell, nb->cell_start, fill, nb->perm);
     hipLaunchKernelGGL(k_sort_cells, dim3(gc), dim3(kBlock), 0, ctx->stream, ncell, nb->cell_start, nb->perm);
     hipLaunchKernelGGL(k_gather_pos, dim3(gp), dim3(kBlock), 0, ctx->stream, n, nb->perm, cell, p->x, p->y,
-                       p->z, nb->px, nb->py, nb->pz, nb->scell, nb->iperm);
+                       p->z, nb->pos, nb->scell, nb->iperm);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err("neighbour build kernels");
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_err("hipStreamSynchronize");
     cleanup();
@@ -389,9 +387,7 @@ extern "C" sph_status sph_neighbors_free(sph_nbr* nb) {
     (void)hipFree(nb->scell);
     (void)hipFree(nb->perm);
     (void)hipFree(nb->iperm);
-    (void)hipFree(nb->px);
-    (void)hipFree(nb->py);
-    (void)hipFree(nb->pz);
+    (void)hipFree(nb->pos);
     delete nb;
     return SPH_OK;
 }

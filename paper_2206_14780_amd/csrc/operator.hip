@@ -8,6 +8,13 @@
 
 namespace sph {
 
+static int32_t env_int(const char* name, int32_t dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    long x = std::strtol(v, nullptr, 10);
+    return x > 0 ? (int32_t)x : dflt;
+}
+
 // ---------------------------------------------------------------------------
 // Gathers between the caller's order and cell order.
 // ---------------------------------------------------------------------------
@@ -18,14 +25,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_props(int64_t n, const int32_
                                                          const uint8_t* __restrict__ t,
                                                          double* __restrict__ om, double* __restrict__ orr,
                                                          double* __restrict__ omu,
-                                                         uint8_t* __restrict__ ot) {
+                                                         uint8_t* __restrict__ ot, double* __restrict__ omr,
+                                                         double* __restrict__ oir) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int32_t o = perm[s];
-    om[s] = m[o];
-    orr[s] = r[o];
+    const double ms = m[o], rs = r[o];
+    om[s] = ms;
+    orr[s] = rs;
     omu[s] = mu[o];
     ot[s] = t[o];
+    omr[s] = ms / rs;
+    oir[s] = 1.0 / rs;
 }
 
 template <typename S, typename D>
@@ -57,19 +68,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter_vec3(int64_t n, const int32_
 
 sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out) {
     const int64_t n = nb->n;
-    double *m = nullptr, *r = nullptr, *mu = nullptr;
+    double *m = nullptr, *r = nullptr, *mu = nullptr, *mr = nullptr, *ir = nullptr;
     uint8_t* t = nullptr;
     SPH_TRY(ctx->ensure_t(kMass, n, &m));
     SPH_TRY(ctx->ensure_t(kRho, n, &r));
     SPH_TRY(ctx->ensure_t(kMu, n, &mu));
     SPH_TRY(ctx->ensure_t(kType, n, &t));
+    SPH_TRY(ctx->ensure_t(kMRho, n, &mr));
+    SPH_TRY(ctx->ensure_t(kInvRho, n, &ir));
     hipLaunchKernelGGL(k_gather_props, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
-                       nb->perm, p->mass, p->rho, p->mu, p->type, m, r, mu, t);
+                       nb->perm, p->mass, p->rho, p->mu, p->type, m, r, mu, t, mr, ir);
     SPH_LAUNCHED("k_gather_props");
     out->mass = m;
     out->rho = r;
     out->mu = mu;
     out->type = t;
+    out->m_rho = mr;
+    out->inv_rho = ir;
     return SPH_OK;
 }
 
@@ -216,6 +231,112 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
     for (; k < width; ++k) sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, pad_col, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Staged matrix build.  One scan per row (the count pass) finds the
+// neighbours, evaluates each pair coefficient once, and records (neighbour,
+// FP64 weight) in a staging buffer together with the row's sum; the fill pass
+// is then a streaming transform that scales the staged weights and writes
+// entry k of the 64 rows of a slice with one coalesced store.  (Evaluating
+// the coefficients in the fill instead re-gathers every neighbour's position
+// and properties, which dominated the build.)  Staging layout: entry k of row
+// r at (r/64) kFillCap 64 + 64 k + r%64.
+// ---------------------------------------------------------------------------
+constexpr int kFillCap = 96;  // staged neighbours per row (longer rows: scan-order build)
+
+__global__ __launch_bounds__(kBlock) void k_row_count_stage(NbrView nv, PartView pv, OpParams op,
+                                                            int32_t* __restrict__ cnt, int32_t* __restrict__ maxcnt,
+                                                            int32_t* __restrict__ stage, double* __restrict__ wstage,
+                                                            double* __restrict__ diag64,
+                                                            double* __restrict__ wsum) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nv.n) return;
+    const int32_t row = (int32_t)b;
+    const int64_t off = (b / kWave) * (int64_t)(kFillCap * kWave) + (b % kWave);
+    int32_t* st = stage + off;
+    double* ws = wstage + off;
+    int32_t c = 0;
+    double d = 1.0, sum = 0.0;
+    if (pv.type[row] == SPH_FLUID) {
+        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+            const double w = pair_w(pv, nv.g, op.avg, row, a, r2);
+            sum += w;
+            if (c < kFillCap) {
+                st[c * kWave] = a;
+                ws[c * kWave] = w;
+            }
+            ++c;
+        });
+        d = 1.0 + op.dt * sum;
+    } else if (op.wall == SPH_WALL_DUMMY) {
+        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+            if (pv.type[a] != SPH_FLUID) return;
+            const double W = pair_W(nv.g, r2);
+            sum += W;
+            if (c < kFillCap) {
+                st[c * kWave] = a;
+                ws[c * kWave] = W;
+            }
+            ++c;
+        });
+        if (!(sum > 0.0)) c = 0;  // identity row
+    }
+    cnt[row] = c;
+    diag64[row] = d;
+    wsum[row] = sum;
+    atomicMax(maxcnt, c);
+}
+
+// One lane per row of a slice (rows >= n write padding).  Same coefficients
+// and row sums as k_row_fill, bit for bit (same weights, same sums).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_row_fill_staged(PartView pv, OpParams op, int64_t n,
+                                                            const int32_t* __restrict__ cnt,
+                                                            const int32_t* __restrict__ stage,
+                                                            const double* __restrict__ wstage,
+                                                            const double* __restrict__ diag64,
+                                                            const double* __restrict__ wsum,
+                                                            const int64_t* __restrict__ sl_ptr,
+                                                            int2* __restrict__ pk, float* __restrict__ lo,
+                                                            int32_t* __restrict__ cols, T* __restrict__ coef,
+                                                            T* __restrict__ dg, double* __restrict__ rs64,
+                                                            int64_t nslices) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nslices * kWave) return;
+    const int64_t s = r / kWave;
+    const int lane = (int)(r % kWave);
+    const bool valid = r < n;
+    const int32_t row = valid ? (int32_t)r : 0;
+    const bool fluid = valid && pv.type[row] == SPH_FLUID;
+    const int32_t c = valid ? cnt[row] : 0;
+    const double D = valid ? diag64[row] : 1.0;
+    const double sW = valid ? wsum[row] : 0.0;
+    const int64_t so = s * (int64_t)(kFillCap * kWave) + lane;
+    const int64_t base = sl_ptr[s] + lane;
+    const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
+    for (int32_t k = 0; k < width; ++k) {
+        int32_t col = row;
+        double cf = 0.0;
+        if (k < c) {
+            col = stage[so + k * kWave];
+            const double w = wstage[so + k * kWave];
+            if (fluid) {
+                const double aba = -op.dt * w;
+                cf = op.jacobi ? aba / D : aba;
+            } else {
+                cf = w / sW;
+            }
+        }
+        sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, col, cf);
+    }
+    if (valid) {
+        // row sums as in k_row_fill: 1/A_rr (Jacobi) or 1 on fluid rows, 2 on
+        // dummy rows with fluid neighbours, 1 on identity rows
+        const double rs = fluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
+        dg[row] = (T)rs;
+        rs64[row] = rs;
+    }
+}
+
 sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op,
                       const double** diag64) {
     double* d = nullptr;
@@ -232,29 +353,42 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
                       const double** diag64, int64_t* nnz_out, int64_t* slots_out) {
     const int64_t n = nb->n;
     const int64_t nslices = ceil_div(n, kWave);
-    int32_t* cnt = nullptr;
-    double *d = nullptr, *ws = nullptr;
+    // SPH_BUILD_LEGACY=1 selects the build with the coefficients evaluated
+    // inside the scan (the reference the staged build is tested against)
+    const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
+    int32_t *cnt = nullptr, *stage = nullptr;
+    double *d = nullptr, *ws = nullptr, *wstage = nullptr;
     int64_t *size = nullptr, *ptr = nullptr;
     SPH_TRY(ctx->ensure_t(kCnt, n, &cnt));
     SPH_TRY(ctx->ensure_t(kDiag64, n, &d));
-    SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
     SPH_TRY(ctx->ensure_t(kSlSize, nslices, &size));
     SPH_TRY(ctx->ensure_t(kSlPtr, nslices + 1, &ptr));
-    hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                       nb->view(), pv, op, cnt, d, ws);
-    unsigned long long* nnz_dev = nullptr;
-    SPH_TRY(ctx->ensure_t(kNnzCount, 1, &nnz_dev));
-    SPH_HIP(hipMemsetAsync(nnz_dev, 0, sizeof(unsigned long long), ctx->stream));
+    unsigned long long* nnz_dev = nullptr;  // [0] nonzeros, [1] longest row
+    SPH_TRY(ctx->ensure_t(kNnzCount, 2, &nnz_dev));
+    SPH_HIP(hipMemsetAsync(nnz_dev, 0, 2 * sizeof(unsigned long long), ctx->stream));
+    int32_t* maxc = reinterpret_cast<int32_t*>(nnz_dev + 1);
+    const dim3 rows_grid((unsigned)ceil_div(n, kBlock));
+    if (legacy) {
+        SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
+        hipLaunchKernelGGL(k_row_count, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, d, ws);
+    } else {
+        SPH_TRY(ctx->ensure_t(kStage, (size_t)nslices * kFillCap * kWave, &stage));
+        SPH_TRY(ctx->ensure_t(kWStage, (size_t)nslices * kFillCap * kWave, &wstage));
+        SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
+        hipLaunchKernelGGL(k_row_count_stage, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, maxc,
+                           stage, wstage, d, ws);
+    }
     hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
                        n, nslices, cnt, size, nnz_dev);
     SPH_LAUNCHED("k_row_count/k_slice_size");
     SPH_TRY(scan_i64(ctx, size, ptr, nslices));
     int64_t nnzp = 0;
-    unsigned long long nnz_true = 0;
+    unsigned long long hcnt[2] = {0, 0};
     SPH_HIP(hipMemcpyAsync(&nnzp, ptr + nslices, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-    SPH_HIP(hipMemcpyAsync(&nnz_true, nnz_dev, sizeof(nnz_true), hipMemcpyDeviceToHost, ctx->stream));
+    SPH_HIP(hipMemcpyAsync(hcnt, nnz_dev, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
     SPH_HIP(hipStreamSynchronize(ctx->stream));
-    if (nnz_out) *nnz_out = (int64_t)nnz_true;
+    const int32_t longest = *reinterpret_cast<const int32_t*>(&hcnt[1]);
+    if (nnz_out) *nnz_out = (int64_t)hcnt[0];
     if (slots_out) *slots_out = nnzp;
     int32_t* cols = nullptr;
     T* coef = nullptr;
@@ -272,9 +406,18 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     double* rs64 = nullptr;
     SPH_TRY(ctx->ensure_t(kDg, n, &dg));
     SPH_TRY(ctx->ensure_t(kRs64, n, &rs64));
-    hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, nb->view(), pv, op, d, ws, ptr, pk, lo, cols, coef, dg, rs64, nslices);
-    SPH_LAUNCHED("k_row_fill");
+    if (!legacy && longest <= kFillCap) {
+        hipLaunchKernelGGL(k_row_fill_staged<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
+                           ctx->stream, pv, op, n, cnt, stage, wstage, d, ws, ptr, pk, lo, cols, coef, dg, rs64,
+                           nslices);
+        SPH_LAUNCHED("k_row_fill_staged");
+    } else {
+        // (after the staged count, a row longer than the staging capacity:
+        // its diagonal and sums are already in d and ws)
+        hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
+                           ctx->stream, nb->view(), pv, op, d, ws, ptr, pk, lo, cols, coef, dg, rs64, nslices);
+        SPH_LAUNCHED("k_row_fill");
+    }
     out->nslices = nslices;
     out->sl_ptr = ptr;
     out->pk = pk;
@@ -292,12 +435,6 @@ template sph_status build_sell<float>(sph_ctx*, const sph_nbr*, const PartView&,
 template sph_status build_sell<double>(sph_ctx*, const sph_nbr*, const PartView&, const OpParams&,
                                        Sell<double>*, const double**, int64_t*, int64_t*);
 
-static int32_t env_int(const char* name, int32_t dflt) {
-    const char* v = std::getenv(name);
-    if (!v || !*v) return dflt;
-    long x = std::strtol(v, nullptr, 10);
-    return x > 0 ? (int32_t)x : dflt;
-}
 
 // Launch geometry of the row kernels.  SPH_APPLY_BLOCK / SPH_APPLY_GRID /
 // SPH_STREAM_BLOCK / SPH_STREAM_GRID override the defaults (tuning sweeps).

@@ -66,7 +66,8 @@ __device__ inline int axis_cells(int32_t c, int32_t n, int32_t per, int32_t (&ou
 template <class F>
 __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) {
     const Grid& g = nv.g;
-    const double xb = nv.px[row], yb = nv.py[row], zb = nv.pz[row];
+    const Pos4 pb = nv.pos[row];
+    const double xb = pb.x, yb = pb.y, zb = pb.z;
     const int32_t c = nv.scell[row];
     const int32_t nx = g.nc[0], ny = g.nc[1];
     const int32_t cx = c % nx;
@@ -98,9 +99,10 @@ __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) 
                 const int32_t end = nv.cell_start[base + xe + 1];
                 for (int32_t a = beg; a < end; ++a) {
                     if (a == row) continue;
-                    double dx = disp(xb, nv.px[a], g.period[0]);
-                    double dy = disp(yb, nv.py[a], g.period[1]);
-                    double dz = disp(zb, nv.pz[a], g.period[2]);
+                    const Pos4 pa = nv.pos[a];
+                    double dx = disp(xb, pa.x, g.period[0]);
+                    double dy = disp(yb, pa.y, g.period[1]);
+                    double dz = disp(zb, pa.z, g.period[2]);
                     double r2 = (dx * dx + dy * dy) + dz * dz;
                     if (r2 < g.cut2) f(a, r2);
                 }
@@ -110,20 +112,20 @@ __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) 
 }
 
 // Pair weight w_ba = -2 mubar m_a F(r)/(rho_a rho_b) >= 0 of row b and
-// neighbour a (eq. kab, diffusive sign).
+// neighbour a (eq. kab, diffusive sign), from the precomputed m_a/rho_a,
+// 1/rho_b and powers of 1/h (one division left: the harmonic mean).
 __device__ inline double pair_w(const PartView& pv, const Grid& g, int avg, int32_t b,
                                 int32_t a, double r2) {
-    double q = sqrt(r2) / g.h;
-    double h2 = g.h * g.h;
-    double F = wendland_f(q) / (h2 * h2 * g.h);
-    double tm = two_mubar(pv.mu[a], pv.mu[b], avg);
-    return -(tm * pv.mass[a] * F) / (pv.rho[a] * pv.rho[b]);
+    const double q = sqrt(r2) * g.inv_h;
+    const double F = wendland_f(q) * g.inv_h5;
+    const double tm = two_mubar(pv.mu[a], pv.mu[b], avg);
+    return -(tm * pv.m_rho[a] * F) * pv.inv_rho[b];
 }
 
 // Kernel value W_ba of the dummy-wall rows (eq. dummyvel).
 __device__ inline double pair_W(const Grid& g, double r2) {
-    double q = sqrt(r2) / g.h;
-    return wendland_w(q) / (g.h * g.h * g.h);
+    const double q = sqrt(r2) * g.inv_h;
+    return wendland_w(q) * g.inv_h3;
 }
 
 // ---------------------------------------------------------------------------

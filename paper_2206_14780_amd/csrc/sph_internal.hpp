@@ -31,6 +31,13 @@ struct Grid {
     int32_t per[3];     // periodic flags
     double h;           // smoothing length
     double cut2;        // (2h)^2, the neighbour predicate's bound
+    double inv_h, inv_h3, inv_h5;  // 1/h, 1/h^3, 1/h^5
+};
+
+// One particle's position in cell order, padded to 32 bytes so that a
+// neighbour candidate costs one load.
+struct alignas(32) Pos4 {
+    double x, y, z, pad;
 };
 
 // Device view of a neighbour handle (cell-sorted positions).
@@ -39,9 +46,7 @@ struct NbrView {
     Grid g;
     const int32_t* cell_start;  // [ncell + 1]
     const int32_t* scell;       // cell id of each sorted particle
-    const double* px;           // sorted positions
-    const double* py;
-    const double* pz;
+    const Pos4* pos;            // sorted positions
 };
 
 // Per-particle operator data in cell order.
@@ -50,6 +55,8 @@ struct PartView {
     const double* rho;
     const double* mu;
     const uint8_t* type;
+    const double* m_rho;    // mass / rho
+    const double* inv_rho;  // 1 / rho
 };
 
 struct OpParams {
@@ -158,11 +165,11 @@ Launch make_launch(int64_t n);
 // Device workspace: named, monotonically growing allocations of a context.
 // ---------------------------------------------------------------------------
 enum Slot : int {
-    kMass, kRho, kMu, kType, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg, kPk, kLo, kRs64,
+    kMass, kRho, kMu, kType, kMRho, kInvRho, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg, kPk, kLo, kRs64,
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,
-    kWarmPart2, kWarmU, kNumSlots
+    kWarmPart2, kWarmU, kStage, kWStage, kNumSlots
 };
 
 }  // namespace sph
@@ -200,9 +207,7 @@ struct sph_nbr {
     int32_t* scell = nullptr;
     int32_t* perm = nullptr;    // sorted -> original
     int32_t* iperm = nullptr;   // original -> sorted
-    double* px = nullptr;
-    double* py = nullptr;
-    double* pz = nullptr;
+    sph::Pos4* pos = nullptr;
     int64_t nnz = -1;           // pair count, computed on demand
 
     sph::NbrView view() const {
@@ -211,9 +216,7 @@ struct sph_nbr {
         v.g = g;
         v.cell_start = cell_start;
         v.scell = scell;
-        v.px = px;
-        v.py = py;
-        v.pz = pz;
+        v.pos = pos;
         return v;
     }
 };

@@ -269,3 +269,24 @@ def test_restart_on_drop_matches_oracle_fp64(ctx):
     assert rep["n_replaced"] == ro["n_replaced"] and rep["n_true_checks"] == ro["n_true_checks"]
     assert abs(rep["iters"] - ro["iters"]) <= 1
     assert rel_l2(X, Xo) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_F32])
+@pytest.mark.parametrize("wall", [W.WALL_DYNAMIC, W.WALL_DUMMY])
+@pytest.mark.parametrize("jacobi", [True, False])
+def test_staged_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, monkeypatch):
+    # the LDS-staged build must reproduce the two-kernel build bit for bit:
+    # same pairs, same summation order, same coefficients and row sums
+    for w in (small_tank(seed=61, wall=wall), W.open_box(14, wall=wall)):
+        g = GpuCase(ctx, w)
+        X = np.random.default_rng(62).normal(size=(w.n, 3))
+        print(f"[build] {w.name} prec={prec} jacobi={jacobi}", flush=True)
+        y_new = g.apply(X, prec, jacobi=jacobi)
+        Xs, rs = g.solve(w.rhs, prec, tol=1e-6)
+        monkeypatch.setenv("SPH_BUILD_LEGACY", "1")
+        y_old = g.apply(X, prec, jacobi=jacobi)
+        Xl, rl = g.solve(w.rhs, prec, tol=1e-6)
+        monkeypatch.delenv("SPH_BUILD_LEGACY")
+        assert np.array_equal(y_new, y_old)
+        assert rs["mat_nnz"] == rl["mat_nnz"] and rs["mat_slots"] == rl["mat_slots"]
+        assert rs["history"] == rl["history"] and np.array_equal(Xs, Xl)
