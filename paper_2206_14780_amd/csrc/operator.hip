@@ -119,40 +119,113 @@ template sph_status scatter_vec3<float>(sph_ctx*, const sph_nbr*, const float*, 
 template sph_status scatter_vec3<double>(sph_ctx*, const sph_nbr*, const double*, void* const[3]);
 
 // ---------------------------------------------------------------------------
-// Matrix build, pass 1: entries per row, FP64 diagonal, dummy-wall kernel sum.
+// Delta-coded slots (see Sell): a step outside [0, kEscape) takes an escape
+// slot carrying the whole jump.
+// ---------------------------------------------------------------------------
+__device__ inline bool needs_escape(int64_t step) { return step < 0 || step >= (int64_t)kEscape; }
+
+// Coefficients are evaluated in FP64 and rounded once to T (FP32 also keeps
+// the rounding remainder).
+__device__ inline void sell_put(float* coef, uint16_t* dcol, float* lo, int64_t i, int32_t step, double c) {
+    const float hi = (float)c;
+    coef[i] = hi;
+    lo[i] = (float)(c - (double)hi);
+    dcol[i] = (uint16_t)step;
+}
+__device__ inline void sell_put(double* coef, uint16_t* dcol, float*, int64_t i, int32_t step, double c) {
+    coef[i] = c;
+    dcol[i] = (uint16_t)step;
+}
+__device__ inline void sell_escape(float* coef, uint16_t* dcol, float* lo, int64_t i, int32_t jump) {
+    coef[i] = __int_as_float(jump);
+    lo[i] = 0.f;
+    dcol[i] = kEscape;
+}
+__device__ inline void sell_escape(double* coef, uint16_t* dcol, float*, int64_t i, int32_t jump) {
+    coef[i] = __longlong_as_double((long long)jump);
+    dcol[i] = kEscape;
+}
+
+// Writes one row's slots in order: put(col, c) per entry (columns as they
+// come), then pad() up to the slice width.  c0 receives the first column.
+template <typename T>
+struct RowWriter {
+    T* coef;
+    uint16_t* dcol;
+    float* lo;
+    int64_t base;  // the lane's first slot
+    int32_t j = 0;
+    int32_t prev = 0;
+    __device__ void put(int32_t col, double c) {
+        if (j > 0) {
+            const int64_t step = (int64_t)col - prev;
+            if (needs_escape(step)) {
+                sell_escape(coef, dcol, lo, base + (int64_t)j * kWave, (int32_t)step);
+                ++j;
+                prev = col;
+            }
+        } else {
+            prev = col;
+        }
+        sell_put(coef, dcol, lo, base + (int64_t)j * kWave, col - prev, c);
+        ++j;
+        prev = col;
+    }
+    __device__ void pad(int32_t width) {
+        for (; j < width; ++j) sell_put(coef, dcol, lo, base + (int64_t)j * kWave, 0, 0.0);
+    }
+};
+
+// Slots of a row with c entries in column order: c plus one escape per step
+// outside [0, kEscape).
+struct SlotCounter {
+    int32_t c = 0, slots = 0, prev = 0;
+    __device__ void add(int32_t col) {
+        if (c > 0 && needs_escape((int64_t)col - prev)) ++slots;
+        ++c;
+        ++slots;
+        prev = col;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Matrix build, pass 1: slots and entries per row, FP64 diagonal, dummy-wall
+// kernel sum.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_row_count(NbrView nv, PartView pv, OpParams op,
-                                                      int32_t* __restrict__ cnt,
+                                                      int32_t* __restrict__ cnt, int32_t* __restrict__ creal,
                                                       double* __restrict__ diag64,
                                                       double* __restrict__ wsum) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nv.n) return;
     const int32_t row = (int32_t)b;
-    int32_t c = 0;
+    SlotCounter sc;
     double d = 1.0, sW = 0.0;
     if (pv.type[row] == SPH_FLUID) {
         double sw = 0.0;
         for_each_neighbor(nv, row, [&](int32_t a, double r2) {
             sw += pair_w(pv, nv.g, op.avg, row, a, r2);
-            ++c;
+            sc.add(a);
         });
         d = 1.0 + op.dt * sw;
     } else if (op.wall == SPH_WALL_DUMMY) {
         for_each_neighbor(nv, row, [&](int32_t a, double r2) {
             if (pv.type[a] != SPH_FLUID) return;
             sW += pair_W(nv.g, r2);
-            ++c;
+            sc.add(a);
         });
-        if (!(sW > 0.0)) c = 0;
+        if (!(sW > 0.0)) sc = SlotCounter{};
     }
-    if (cnt) cnt[row] = c;
+    if (cnt) cnt[row] = sc.slots;
+    if (creal) creal[row] = sc.c;
     diag64[row] = d;
     if (wsum) wsum[row] = sW;
 }
 
-// Slice size = 64 x (longest row of the slice).
+// Slice size = 64 x (most slots of a row of the slice); nnz += entries.
 __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslices,
                                                        const int32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ creal,
                                                        int64_t* __restrict__ size,
                                                        unsigned long long* __restrict__ nnz) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,51 +236,38 @@ __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslice
         int64_t r = s * kWave + l;
         if (r < n) {
             w = max(w, cnt[r]);
-            tot += cnt[r];
+            tot += creal[r];
         }
     }
     size[s] = (int64_t)w * kWave;
     atomicAdd(nnz, (unsigned long long)tot);
 }
 
-// Pass 2: write columns and coefficients.  Coefficients are evaluated in
-// FP64 and rounded once to T (FP32 also keeps the rounding remainder).
-__device__ inline void sell_store(int2* pk, float* lo, int32_t*, float*, int64_t i, int32_t col, double c) {
-    const float hi = (float)c;
-    pk[i] = make_int2(col, __float_as_int(hi));
-    lo[i] = (float)(c - (double)hi);
-}
-__device__ inline void sell_store(int2*, float*, int32_t* cols, double* coef, int64_t i, int32_t col, double c) {
-    cols[i] = col;
-    coef[i] = c;
-}
-
+// Pass 2: write the slots (coefficients evaluated inside the scan).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, OpParams op,
                                                      const double* __restrict__ diag64,
                                                      const double* __restrict__ wsum,
-                                                     const int64_t* __restrict__ sl_ptr, int2* __restrict__ pk,
-                                                     float* __restrict__ lo, int32_t* __restrict__ cols,
-                                                     T* __restrict__ coef, T* __restrict__ dg,
+                                                     const int64_t* __restrict__ sl_ptr, T* __restrict__ coef,
+                                                     uint16_t* __restrict__ dcol, float* __restrict__ lo,
+                                                     int32_t* __restrict__ c0, T* __restrict__ dg,
                                                      double* __restrict__ rs64, int64_t nslices) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nslices * kWave) return;
     const int64_t s = r / kWave;
     const int lane = (int)(r % kWave);
-    const int64_t base = sl_ptr[s] + lane;
     const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
-    int32_t k = 0;
-    int32_t pad_col = 0;
+    RowWriter<T> wr{coef, dcol, lo, sl_ptr[s] + lane};
     if (r < nv.n) {
         const int32_t row = (int32_t)r;
-        pad_col = row;
+        int32_t first = row;
         const double D = diag64[row];
         if (pv.type[row] == SPH_FLUID) {
             for_each_neighbor(nv, row, [&](int32_t a, double r2) {
                 double aba = -op.dt * pair_w(pv, nv.g, op.avg, row, a, r2);
                 double c = op.jacobi ? aba / D : aba;
-                sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, a, c);
-                ++k;
+                if (wr.j == 0) first = a;
+                wr.put(a, c);
             });
             // row sum: (A 1)_r = 1 (eqs. diag, offdiag), scaled by 1/A_rr with Jacobi
             const double rs = op.jacobi ? 1.0 / D : 1.0;
@@ -219,16 +279,17 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
             if (op.wall == SPH_WALL_DUMMY && sW > 0.0) {
                 for_each_neighbor(nv, row, [&](int32_t a, double r2) {
                     if (pv.type[a] != SPH_FLUID) return;
-                    sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, a, pair_W(nv.g, r2) / sW);
-                    ++k;
+                    if (wr.j == 0) first = a;
+                    wr.put(a, pair_W(nv.g, r2) / sW);
                 });
                 rs = 2.0;  // 1 + sum_a W_ra / sum_a W_ra (eq. implicit-system-dummy-full)
             }
             dg[row] = (T)rs;
             rs64[row] = rs;
         }
+        c0[row] = first;
     }
-    for (; k < width; ++k) sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, pad_col, 0.0);
+    wr.pad(width);
 }
 
 // ---------------------------------------------------------------------------
@@ -244,7 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
 constexpr int kFillCap = 96;  // staged neighbours per row (longer rows: scan-order build)
 
 __global__ __launch_bounds__(kBlock) void k_row_count_stage(NbrView nv, PartView pv, OpParams op,
-                                                            int32_t* __restrict__ cnt, int32_t* __restrict__ maxcnt,
+                                                            int32_t* __restrict__ cnt, int32_t* __restrict__ creal,
+                                                            int32_t* __restrict__ maxcnt,
                                                             int32_t* __restrict__ stage, double* __restrict__ wstage,
                                                             double* __restrict__ diag64,
                                                             double* __restrict__ wsum) {
@@ -254,17 +316,17 @@ __global__ __launch_bounds__(kBlock) void k_row_count_stage(NbrView nv, PartView
     const int64_t off = (b / kWave) * (int64_t)(kFillCap * kWave) + (b % kWave);
     int32_t* st = stage + off;
     double* ws = wstage + off;
-    int32_t c = 0;
+    SlotCounter sc;
     double d = 1.0, sum = 0.0;
     if (pv.type[row] == SPH_FLUID) {
         for_each_neighbor(nv, row, [&](int32_t a, double r2) {
             const double w = pair_w(pv, nv.g, op.avg, row, a, r2);
             sum += w;
-            if (c < kFillCap) {
-                st[c * kWave] = a;
-                ws[c * kWave] = w;
+            if (sc.c < kFillCap) {
+                st[sc.c * kWave] = a;
+                ws[sc.c * kWave] = w;
             }
-            ++c;
+            sc.add(a);
         });
         d = 1.0 + op.dt * sum;
     } else if (op.wall == SPH_WALL_DUMMY) {
@@ -272,34 +334,34 @@ __global__ __launch_bounds__(kBlock) void k_row_count_stage(NbrView nv, PartView
             if (pv.type[a] != SPH_FLUID) return;
             const double W = pair_W(nv.g, r2);
             sum += W;
-            if (c < kFillCap) {
-                st[c * kWave] = a;
-                ws[c * kWave] = W;
+            if (sc.c < kFillCap) {
+                st[sc.c * kWave] = a;
+                ws[sc.c * kWave] = W;
             }
-            ++c;
+            sc.add(a);
         });
-        if (!(sum > 0.0)) c = 0;  // identity row
+        if (!(sum > 0.0)) sc = SlotCounter{};  // identity row
     }
-    cnt[row] = c;
+    cnt[row] = sc.slots;
+    creal[row] = sc.c;
     diag64[row] = d;
     wsum[row] = sum;
-    atomicMax(maxcnt, c);
+    atomicMax(maxcnt, sc.c);
 }
 
 // One lane per row of a slice (rows >= n write padding).  Same coefficients
 // and row sums as k_row_fill, bit for bit (same weights, same sums).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_row_fill_staged(PartView pv, OpParams op, int64_t n,
-                                                            const int32_t* __restrict__ cnt,
+                                                            const int32_t* __restrict__ creal,
                                                             const int32_t* __restrict__ stage,
                                                             const double* __restrict__ wstage,
                                                             const double* __restrict__ diag64,
                                                             const double* __restrict__ wsum,
-                                                            const int64_t* __restrict__ sl_ptr,
-                                                            int2* __restrict__ pk, float* __restrict__ lo,
-                                                            int32_t* __restrict__ cols, T* __restrict__ coef,
-                                                            T* __restrict__ dg, double* __restrict__ rs64,
-                                                            int64_t nslices) {
+                                                            const int64_t* __restrict__ sl_ptr, T* __restrict__ coef,
+                                                            uint16_t* __restrict__ dcol, float* __restrict__ lo,
+                                                            int32_t* __restrict__ c0, T* __restrict__ dg,
+                                                            double* __restrict__ rs64, int64_t nslices) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nslices * kWave) return;
     const int64_t s = r / kWave;
@@ -307,28 +369,27 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_staged(PartView pv, OpParam
     const bool valid = r < n;
     const int32_t row = valid ? (int32_t)r : 0;
     const bool fluid = valid && pv.type[row] == SPH_FLUID;
-    const int32_t c = valid ? cnt[row] : 0;
+    const int32_t c = valid ? creal[row] : 0;
     const double D = valid ? diag64[row] : 1.0;
     const double sW = valid ? wsum[row] : 0.0;
     const int64_t so = s * (int64_t)(kFillCap * kWave) + lane;
-    const int64_t base = sl_ptr[s] + lane;
     const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
-    for (int32_t k = 0; k < width; ++k) {
-        int32_t col = row;
-        double cf = 0.0;
-        if (k < c) {
-            col = stage[so + k * kWave];
-            const double w = wstage[so + k * kWave];
-            if (fluid) {
-                const double aba = -op.dt * w;
-                cf = op.jacobi ? aba / D : aba;
-            } else {
-                cf = w / sW;
-            }
+    RowWriter<T> wr{coef, dcol, lo, sl_ptr[s] + lane};
+    for (int32_t k = 0; k < c; ++k) {
+        const int32_t col = stage[so + k * kWave];
+        const double w = wstage[so + k * kWave];
+        double cf;
+        if (fluid) {
+            const double aba = -op.dt * w;
+            cf = op.jacobi ? aba / D : aba;
+        } else {
+            cf = w / sW;
         }
-        sell_store(pk, lo, cols, coef, base + (int64_t)k * kWave, col, cf);
+        wr.put(col, cf);
     }
+    wr.pad(width);
     if (valid) {
+        c0[row] = c > 0 ? stage[so] : row;
         // row sums as in k_row_fill: 1/A_rr (Jacobi) or 1 on fluid rows, 2 on
         // dummy rows with fluid neighbours, 1 on identity rows
         const double rs = fluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
@@ -342,7 +403,7 @@ sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     double* d = nullptr;
     SPH_TRY(ctx->ensure_t(kDiag64, nb->n, &d));
     hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(nb->n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                       nb->view(), pv, op, (int32_t*)nullptr, d, (double*)nullptr);
+                       nb->view(), pv, op, (int32_t*)nullptr, (int32_t*)nullptr, d, (double*)nullptr);
     SPH_LAUNCHED("k_row_count");
     *diag64 = d;
     return SPH_OK;
@@ -356,10 +417,11 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     // SPH_BUILD_LEGACY=1 selects the build with the coefficients evaluated
     // inside the scan (the reference the staged build is tested against)
     const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
-    int32_t *cnt = nullptr, *stage = nullptr;
+    int32_t *cnt = nullptr, *creal = nullptr, *stage = nullptr;
     double *d = nullptr, *ws = nullptr, *wstage = nullptr;
     int64_t *size = nullptr, *ptr = nullptr;
     SPH_TRY(ctx->ensure_t(kCnt, n, &cnt));
+    SPH_TRY(ctx->ensure_t(kCntReal, n, &creal));
     SPH_TRY(ctx->ensure_t(kDiag64, n, &d));
     SPH_TRY(ctx->ensure_t(kSlSize, nslices, &size));
     SPH_TRY(ctx->ensure_t(kSlPtr, nslices + 1, &ptr));
@@ -370,16 +432,17 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     const dim3 rows_grid((unsigned)ceil_div(n, kBlock));
     if (legacy) {
         SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
-        hipLaunchKernelGGL(k_row_count, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, d, ws);
+        hipLaunchKernelGGL(k_row_count, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal, d,
+                           ws);
     } else {
         SPH_TRY(ctx->ensure_t(kStage, (size_t)nslices * kFillCap * kWave, &stage));
         SPH_TRY(ctx->ensure_t(kWStage, (size_t)nslices * kFillCap * kWave, &wstage));
         SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
-        hipLaunchKernelGGL(k_row_count_stage, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, maxc,
-                           stage, wstage, d, ws);
+        hipLaunchKernelGGL(k_row_count_stage, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal,
+                           maxc, stage, wstage, d, ws);
     }
     hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
-                       n, nslices, cnt, size, nnz_dev);
+                       n, nslices, cnt, creal, size, nnz_dev);
     SPH_LAUNCHED("k_row_count/k_slice_size");
     SPH_TRY(scan_i64(ctx, size, ptr, nslices));
     int64_t nnzp = 0;
@@ -390,40 +453,37 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     const int32_t longest = *reinterpret_cast<const int32_t*>(&hcnt[1]);
     if (nnz_out) *nnz_out = (int64_t)hcnt[0];
     if (slots_out) *slots_out = nnzp;
-    int32_t* cols = nullptr;
     T* coef = nullptr;
-    int2* pk = nullptr;
+    uint16_t* dcol = nullptr;
     float* lo = nullptr;
+    int32_t* c0 = nullptr;
     T* dg = nullptr;
     const size_t ns = (size_t)(nnzp > 0 ? nnzp : 1);
-    if constexpr (sizeof(T) == 4) {
-        SPH_TRY(ctx->ensure_t(kPk, ns, &pk));
-        SPH_TRY(ctx->ensure_t(kLo, ns, &lo));
-    } else {
-        SPH_TRY(ctx->ensure_t(kCols, ns, &cols));
-        SPH_TRY(ctx->ensure_t(kCoef, ns, &coef));
-    }
+    SPH_TRY(ctx->ensure_t(kCoef, ns, &coef));
+    SPH_TRY(ctx->ensure_t(kDcol, ns, &dcol));
+    if constexpr (sizeof(T) == 4) SPH_TRY(ctx->ensure_t(kLo, ns, &lo));
+    SPH_TRY(ctx->ensure_t(kC0, n, &c0));
     double* rs64 = nullptr;
     SPH_TRY(ctx->ensure_t(kDg, n, &dg));
     SPH_TRY(ctx->ensure_t(kRs64, n, &rs64));
     if (!legacy && longest <= kFillCap) {
         hipLaunchKernelGGL(k_row_fill_staged<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
-                           ctx->stream, pv, op, n, cnt, stage, wstage, d, ws, ptr, pk, lo, cols, coef, dg, rs64,
+                           ctx->stream, pv, op, n, creal, stage, wstage, d, ws, ptr, coef, dcol, lo, c0, dg, rs64,
                            nslices);
         SPH_LAUNCHED("k_row_fill_staged");
     } else {
         // (after the staged count, a row longer than the staging capacity:
         // its diagonal and sums are already in d and ws)
         hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
-                           ctx->stream, nb->view(), pv, op, d, ws, ptr, pk, lo, cols, coef, dg, rs64, nslices);
+                           ctx->stream, nb->view(), pv, op, d, ws, ptr, coef, dcol, lo, c0, dg, rs64, nslices);
         SPH_LAUNCHED("k_row_fill");
     }
     out->nslices = nslices;
     out->sl_ptr = ptr;
-    out->pk = pk;
-    out->lo = lo;
-    out->cols = cols;
     out->coef = coef;
+    out->dcol = dcol;
+    out->lo = lo;
+    out->c0 = c0;
     out->dg = dg;
     out->rs64 = rs64;
     if (diag64) *diag64 = d;

@@ -44,68 +44,70 @@ __device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V
     }
 }
 
-// One stored entry of the cached matrix: column and coefficient.
-__device__ inline void sell_ld(const Sell<float>& A, int64_t i, int32_t& c, float& w) {
-    const int2 v = A.pk[i];
-    c = v.x;
-    w = __int_as_float(v.y);
-}
-__device__ inline void sell_ld(const Sell<double>& A, int64_t i, int32_t& c, double& w) {
-    c = A.cols[i];
-    w = A.coef[i];
-}
-
 // Low part of an FP32 coefficient (c64 - (double)hi); FP64 matrices are exact.
 __device__ inline double sell_lo(const Sell<float>& A, int64_t i) { return (double)A.lo[i]; }
 __device__ inline double sell_lo(const Sell<double>&, int64_t) { return 0.0; }
 
+// Column jump held in the coefficient bits of an escape slot.
+__device__ inline int32_t jump_bits(float w) { return __float_as_int(w); }
+__device__ inline int32_t jump_bits(double w) { return (int32_t)__double_as_longlong(w); }
+
 constexpr int kGroup = 8;  // entries per software-pipelined group
+
+// Raw slots of one group (zero beyond the row's width).
+template <typename T, bool RES>
+__device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width, int32_t k0, T (&w)[kGroup],
+                                  uint16_t (&d)[kGroup], double (&l)[kGroup]) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+        const int32_t k = k0 + u;
+        if (k < width) {
+            const int64_t i = base + (int64_t)k * kWave;
+            w[u] = A.coef[i];
+            d[u] = A.dcol[i];
+            l[u] = RES ? sell_lo(A, i) : 0.0;
+        } else {
+            w[u] = T(0);
+            d[u] = 0;
+            l[u] = 0.0;
+        }
+    }
+}
 
 // sum_k coef[r,k] (x[col[r,k]] - x_r) for the row of this lane (the operator's
 // difference form: rounding scales with the local variation of x, not with x,
 // so smooth fields keep their accuracy in FP32).  `base` is the lane's first
 // slot, `width` the slice width (uniform across the wave).  The loop is
-// software-pipelined: the gathers of group g are issued before the column and
-// coefficient loads of group g + 1, so the L2 latency of the gathers and the
-// HBM latency of the matrix stream overlap.  RES accumulates in FP64 with the
-// FP64-accurate coefficients; x may then be of another precision XT than the
-// matrix (an FP64 solution under an FP32 operator).
+// software-pipelined: the gathers of group g are issued before the slot loads
+// of group g + 1, so the L2 latency of the gathers and the HBM latency of the
+// matrix stream overlap; the column steps of a group are summed before its
+// gathers.  RES accumulates in FP64 with the FP64-accurate coefficients; x
+// may then be of another precision XT than the matrix (an FP64 solution
+// under an FP32 operator).
 template <typename T, bool RES, typename ACC, typename XT = T>
 __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, int32_t row,
                                 const XT* __restrict__ x, const V3<XT>& xs, ACC& a0, ACC& a1, ACC& a2) {
-    int32_t cc[kGroup];
-    T cw[kGroup];
-    double cl[kGroup];
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-        if (u < width) {
-            sell_ld(A, base + (int64_t)u * kWave, cc[u], cw[u]);
-            cl[u] = RES ? sell_lo(A, base + (int64_t)u * kWave) : 0.0;
-        } else {
-            cc[u] = row;
-            cw[u] = T(0);
-            cl[u] = 0.0;
-        }
-    }
+    int32_t col = A.c0[row];
+    T rw[kGroup];
+    uint16_t rd[kGroup];
+    double rl[kGroup];
+    sell_group<T, RES>(A, base, width, 0, rw, rd, rl);
     for (int32_t k0 = 0; k0 < width; k0 += kGroup) {
+        int32_t cc[kGroup];
+        T cw[kGroup];
+        double cl[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const bool esc = rd[u] == kEscape;
+            col += esc ? jump_bits(rw[u]) : (int32_t)rd[u];
+            cc[u] = col;
+            cw[u] = esc ? T(0) : rw[u];
+            cl[u] = esc ? 0.0 : rl[u];
+        }
         V3<XT> xv[kGroup];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) xv[u] = ld3(x, cc[u]);
-        int32_t nc[kGroup];
-        T nw[kGroup];
-        double nl[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            const int32_t k = k0 + kGroup + u;
-            if (k < width) {
-                sell_ld(A, base + (int64_t)k * kWave, nc[u], nw[u]);
-                nl[u] = RES ? sell_lo(A, base + (int64_t)k * kWave) : 0.0;
-            } else {
-                nc[u] = row;
-                nw[u] = T(0);
-                nl[u] = 0.0;
-            }
-        }
+        sell_group<T, RES>(A, base, width, k0 + kGroup, rw, rd, rl);
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
             if constexpr (RES) {
@@ -118,12 +120,6 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
                 a1 = fma_t(cw[u], xv[u].y - xs.y, a1);
                 a2 = fma_t(cw[u], xv[u].z - xs.z, a2);
             }
-        }
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            cc[u] = nc[u];
-            cw[u] = nw[u];
-            cl[u] = nl[u];
         }
     }
 }

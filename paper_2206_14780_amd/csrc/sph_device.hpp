@@ -40,14 +40,18 @@ __device__ inline double two_mubar(double ma, double mb, int avg) {
     return ma + mb;
 }
 
-// Distinct cells of the {c-1, c, c+1} block along one axis (periodic axes
-// with fewer than three cells visit each of their cells once).
+// Distinct cells of the {c-1, c, c+1} block along one axis, ascending
+// (periodic axes with fewer than three cells visit each of their cells once).
 __device__ inline int axis_cells(int32_t c, int32_t n, int32_t per, int32_t (&out)[3]) {
     if (per) {
         if (n >= 3) {
-            out[0] = c > 0 ? c - 1 : n - 1;
-            out[1] = c;
-            out[2] = c < n - 1 ? c + 1 : 0;
+            if (c == 0) {
+                out[0] = 0; out[1] = 1; out[2] = n - 1;
+            } else if (c == n - 1) {
+                out[0] = 0; out[1] = n - 2; out[2] = n - 1;
+            } else {
+                out[0] = c - 1; out[1] = c; out[2] = c + 1;
+            }
             return 3;
         }
         for (int i = 0; i < n; ++i) out[i] = i;
@@ -62,7 +66,8 @@ __device__ inline int axis_cells(int32_t c, int32_t n, int32_t per, int32_t (&ou
 // Calls f(a, r2) for every neighbour a of sorted particle `row` (a != row,
 // r2 = |r_row - r_a|^2 < (2h)^2), visiting the 3x3x3 cell block around the
 // particle's cell as at most 9 runs of consecutive cells along x (a wrapped
-// periodic x adds a second run).
+// periodic x adds a second run), in ascending cell order, so that neighbours
+// come in ascending index order.
 template <class F>
 __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) {
     const Grid& g = nv.g;
@@ -80,7 +85,7 @@ __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) 
     int32_t a0, b0, a1 = 1, b1 = 0;
     if (g.per[0] && nx >= 3) {
         if (cx == 0) { a0 = 0; b0 = 1; a1 = nx - 1; b1 = nx - 1; }
-        else if (cx == nx - 1) { a0 = nx - 2; b0 = nx - 1; a1 = 0; b1 = 0; }
+        else if (cx == nx - 1) { a0 = 0; b0 = 0; a1 = nx - 2; b1 = nx - 1; }
         else { a0 = cx - 1; b0 = cx + 1; }
     } else if (g.per[0]) {
         a0 = 0; b0 = nx - 1;

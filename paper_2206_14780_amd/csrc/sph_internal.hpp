@@ -67,24 +67,29 @@ struct OpParams {
 };
 
 // Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).
-// Entry k of row r = s*64 + l lives at slot sl_ptr[s] + k*64 + l; rows
-// shorter than their slice are padded with (col = r, coef = 0).  The operator
-// is applied in difference form, y_r = rs_r x_r + sum_k coef[r,k] (x_col - x_r),
+// Entry k of row r = s*64 + l lives at slot sl_ptr[s] + k*64 + l.  Columns
+// are delta coded: a row's columns ascend; the row starts at column c0[r]
+// and each slot adds its 16-bit step dcol (the first entry steps by 0).  A
+// step that does not fit takes an escape slot (dcol = kEscape) whose
+// coefficient bits hold the whole jump and which contributes nothing.  Rows
+// shorter than their slice are padded with (step 0, coef 0).  The operator is
+// applied in difference form, y_r = rs_r x_r + sum_k coef[r,k] (x_col - x_r),
 // with rs_r the row sum of the matrix, which the structure of A fixes exactly
 // (1/A_rr for a Jacobi-scaled fluid row, 1 unscaled, 2 for a dummy-wall row
-// with fluid neighbours, 1 for identity rows).
-//   FP32: pk[slot] = (col, bits of the coefficient rounded to FP32) and
-//         lo[slot] = coefficient - (double)hi, so hi + lo carries ~48 bits
-//         for the FP64-accurate residual;
-//   FP64: cols[slot], coef[slot].
+// with fluid neighbours, 1 for identity rows).  The coefficient is FP64
+// evaluated and rounded once to T; FP32 keeps the remainder
+// lo = coefficient - (double)coef, so coef + lo carries ~48 bits for the
+// FP64-accurate residual.
+constexpr uint16_t kEscape = 0xFFFF;
+
 template <typename T>
 struct Sell {
     int64_t nslices;
     const int64_t* sl_ptr;  // [nslices + 1]
-    const int2* pk;         // FP32 only
-    const float* lo;        // FP32 only
-    const int32_t* cols;    // FP64 only
-    const T* coef;          // FP64 only
+    const T* coef;          // per slot
+    const uint16_t* dcol;   // per slot: column step or kEscape
+    const float* lo;        // per slot, FP32 only
+    const int32_t* c0;      // per row: first column (the row itself if empty)
     const T* dg;            // row sum of the (scaled) matrix, per row
     const double* rs64;     // the same row sums in FP64
 };
@@ -165,7 +170,7 @@ Launch make_launch(int64_t n);
 // Device workspace: named, monotonically growing allocations of a context.
 // ---------------------------------------------------------------------------
 enum Slot : int {
-    kMass, kRho, kMu, kType, kMRho, kInvRho, kCnt, kDiag64, kWsum, kSlSize, kSlPtr, kCols, kCoef, kDg, kPk, kLo, kRs64,
+    kMass, kRho, kMu, kType, kMRho, kInvRho, kCnt, kCntReal, kDiag64, kWsum, kSlSize, kSlPtr, kCoef, kDcol, kC0, kDg, kLo, kRs64,
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,

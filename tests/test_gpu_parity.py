@@ -290,3 +290,49 @@ def test_staged_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, m
         assert np.array_equal(y_new, y_old)
         assert rs["mat_nnz"] == rl["mat_nnz"] and rs["mat_slots"] == rl["mat_slots"]
         assert rs["history"] == rl["history"] and np.array_equal(Xs, Xl)
+
+
+def _wide_slab():
+    """180 x 180 x 8 jittered fluid, periodic x and y, three dummy wall layers
+    below and above: a layer of cells holds ~84k particles, so the column
+    steps between cell layers, and across the periodic y seam, exceed 16 bits
+    and the cached matrix needs escape slots."""
+    rng = np.random.default_rng(71)
+    n = (180, 180, 8)
+    pos, pt = W.lattice(n, 1.0, walls=((False, False), (False, False), (True, True)), jitter=0.1,
+                        rng=rng)
+    N = pos.shape[0]
+    perm = rng.permutation(N)
+    pos, pt = pos[perm], pt[perm]
+    mu = 10.0 ** rng.uniform(0.0, 2.0, N)
+    rho = np.ones(N)
+    B = rng.normal(size=(N, 3))
+    B[pt == W.WALL] = 0.0
+    return W.Workload("wide_slab", pos, rho.copy(), rho, mu, pt, np.array([0.0, 0.0, -3.0]),
+                      np.array([180.0, 180.0, 11.0]), np.array([1, 1, 0]), 1.3, 30.0 / mu.max(),
+                      W.WALL_DUMMY, W.AVG_HARMONIC, B, None, 1e-6)
+
+
+@pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_F32])
+def test_escape_slots_on_wide_layers(ctx, prec, monkeypatch):
+    w = _wide_slab()
+    g = GpuCase(ctx, w)
+    print(f"[escape] {w.name} n={w.n} prec={prec}", flush=True)
+    X = np.random.default_rng(72).normal(size=(w.n, 3))
+    if prec == S.SPH_F32:
+        X = X.astype(np.float32).astype(np.float64)
+    Y = g.apply(X, prec, jacobi=True)
+    op = oracle_op(w, jacobi=True)
+    Yo = op.apply(X)
+    D = oracle_op(w, jacobi=False, nbr=(op.row_ptr, op.cols)).diag()
+    bound = apply_bound(D, X, F64_U if prec == S.SPH_F64 else F32_U, True)
+    assert np.all(np.abs(Y - Yo).max(axis=1) <= bound)
+    Xs, rs = g.solve(w.rhs, prec, tol=1e-6, max_iter=200)
+    # 69 x 69 x 5 cells of ~19 particles: consecutive z layers of the stencil
+    # are ~88k columns apart, so every interior row carries escape slots
+    assert rs["status"] == S.SPH_OK
+    monkeypatch.setenv("SPH_BUILD_LEGACY", "1")
+    Yl = g.apply(X, prec, jacobi=True)
+    Xl, rl = g.solve(w.rhs, prec, tol=1e-6, max_iter=200)
+    monkeypatch.delenv("SPH_BUILD_LEGACY")
+    assert np.array_equal(Y, Yl) and rs["history"] == rl["history"]
