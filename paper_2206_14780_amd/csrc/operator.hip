@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_props(int64_t n, const int32_
                                                          const uint8_t* __restrict__ t,
                                                          double* __restrict__ om, double* __restrict__ orr,
                                                          double* __restrict__ omu,
-                                                         uint8_t* __restrict__ ot, double* __restrict__ omr,
+                                                         uint8_t* __restrict__ ot, double2* __restrict__ omr,
                                                          double* __restrict__ oir) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -33,9 +33,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_props(int64_t n, const int32_
     const double ms = m[o], rs = r[o];
     om[s] = ms;
     orr[s] = rs;
-    omu[s] = mu[o];
+    const double mus = mu[o];
+    omu[s] = mus;
     ot[s] = t[o];
-    omr[s] = ms / rs;
+    omr[s] = make_double2(mus, ms / rs);
     oir[s] = 1.0 / rs;
 }
 
@@ -68,13 +69,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_vec3(int64_t n, const int32_
 
 sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out) {
     const int64_t n = nb->n;
-    double *m = nullptr, *r = nullptr, *mu = nullptr, *mr = nullptr, *ir = nullptr;
+    double *m = nullptr, *r = nullptr, *mu = nullptr, *ir = nullptr;
+    double2* mr = nullptr;
     uint8_t* t = nullptr;
     SPH_TRY(ctx->ensure_t(kMass, n, &m));
     SPH_TRY(ctx->ensure_t(kRho, n, &r));
     SPH_TRY(ctx->ensure_t(kMu, n, &mu));
     SPH_TRY(ctx->ensure_t(kType, n, &t));
-    SPH_TRY(ctx->ensure_t(kMRho, n, &mr));
+    SPH_TRY(ctx->ensure_t(kMuMr, n, &mr));
     SPH_TRY(ctx->ensure_t(kInvRho, n, &ir));
     hipLaunchKernelGGL(k_gather_props, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
                        nb->perm, p->mass, p->rho, p->mu, p->type, m, r, mu, t, mr, ir);
@@ -83,7 +85,7 @@ sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p,
     out->rho = r;
     out->mu = mu;
     out->type = t;
-    out->m_rho = mr;
+    out->mu_mr = mr;
     out->inv_rho = ir;
     return SPH_OK;
 }
@@ -228,19 +230,30 @@ __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslice
                                                        const int32_t* __restrict__ creal,
                                                        int64_t* __restrict__ size,
                                                        unsigned long long* __restrict__ nnz) {
+    // nnz[0]: nonzeros; the low 32 bits of nnz[1]: longest row (nonzeros)
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices) return;
-    int32_t w = 0;
+    int32_t w = 0, longest = 0;
     int64_t tot = 0;
-    for (int l = 0; l < kWave; ++l) {
-        int64_t r = s * kWave + l;
-        if (r < n) {
-            w = max(w, cnt[r]);
-            tot += creal[r];
+    if (s < nslices) {
+        for (int l = 0; l < kWave; ++l) {
+            int64_t r = s * kWave + l;
+            if (r < n) {
+                w = max(w, cnt[r]);
+                longest = max(longest, creal[r]);
+                tot += creal[r];
+            }
         }
+        size[s] = (int64_t)w * kWave;
     }
-    size[s] = (int64_t)w * kWave;
-    atomicAdd(nnz, (unsigned long long)tot);
+    // one atomic of each kind per wave
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, kWave);
+        longest = max(longest, __shfl_xor(longest, o, kWave));
+    }
+    if ((threadIdx.x % kWave) == 0 && tot > 0) {
+        atomicAdd(nnz, (unsigned long long)tot);
+        atomicMax(reinterpret_cast<int32_t*>(nnz + 1), longest);
+    }
 }
 
 // Pass 2: write the slots (coefficients evaluated inside the scan).
@@ -293,108 +306,165 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
 }
 
 // ---------------------------------------------------------------------------
-// Staged matrix build.  One scan per row (the count pass) finds the
-// neighbours, evaluates each pair coefficient once, and records (neighbour,
-// FP64 weight) in a staging buffer together with the row's sum; the fill pass
-// is then a streaming transform that scales the staged weights and writes
-// entry k of the 64 rows of a slice with one coalesced store.  (Evaluating
-// the coefficients in the fill instead re-gathers every neighbour's position
-// and properties, which dominated the build.)  Staging layout: entry k of row
-// r at (r/64) kFillCap 64 + 64 k + r%64.
+// List-based matrix build (the default).
+//
+// k_row_scan: one thread per row runs the neighbour scan, counts entries and
+//   slots and records the neighbour indices.  The lanes of a wave reach their
+//   k-th neighbour at different points of the scan, so a direct store of each
+//   index would scatter partial cache lines (several times the list size
+//   written to HBM); each lane instead collects kChunk indices in LDS and
+//   writes them as one 64-byte segment.  List layout: entry k of row r sits
+//   at ((r/64 * kChunks + k/kChunk) * 64 + r%64) * kChunk + k%kChunk.
+// k_row_fill_list: one lane per row of a slice, the lanes walking their
+//   lists in step: the pair weights in list order (= scan order) give the
+//   row sum and the FP64 diagonal and are kept, slot-major (entry k of the
+//   64 rows of a slice written together); a second walk scales them into the
+//   slots, which the lanes also write together.  A row with more than
+//   kListCap neighbours keeps no list and is rescanned here.
+// Same pairs, summation order and coefficients as the scan-order build.
 // ---------------------------------------------------------------------------
-constexpr int kFillCap = 96;  // staged neighbours per row (longer rows: scan-order build)
+constexpr int kChunk = 16;                    // indices per segment
+constexpr int kListCap = 96;                  // listed neighbours per row
+constexpr int kChunks = kListCap / kChunk;
+constexpr int kBufStride = kChunk + 1;        // LDS words per lane (odd: no bank conflicts)
+static_assert(kListCap % kChunk == 0, "whole segments");
 
-__global__ __launch_bounds__(kBlock) void k_row_count_stage(NbrView nv, PartView pv, OpParams op,
-                                                            int32_t* __restrict__ cnt, int32_t* __restrict__ creal,
-                                                            int32_t* __restrict__ maxcnt,
-                                                            int32_t* __restrict__ stage, double* __restrict__ wstage,
-                                                            double* __restrict__ diag64,
-                                                            double* __restrict__ wsum) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nv.n) return;
-    const int32_t row = (int32_t)b;
-    const int64_t off = (b / kWave) * (int64_t)(kFillCap * kWave) + (b % kWave);
-    int32_t* st = stage + off;
-    double* ws = wstage + off;
-    SlotCounter sc;
-    double d = 1.0, sum = 0.0;
-    if (pv.type[row] == SPH_FLUID) {
-        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
-            const double w = pair_w(pv, nv.g, op.avg, row, a, r2);
-            sum += w;
-            if (sc.c < kFillCap) {
-                st[sc.c * kWave] = a;
-                ws[sc.c * kWave] = w;
-            }
-            sc.add(a);
-        });
-        d = 1.0 + op.dt * sum;
-    } else if (op.wall == SPH_WALL_DUMMY) {
-        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
-            if (pv.type[a] != SPH_FLUID) return;
-            const double W = pair_W(nv.g, r2);
-            sum += W;
-            if (sc.c < kFillCap) {
-                st[sc.c * kWave] = a;
-                ws[sc.c * kWave] = W;
-            }
-            sc.add(a);
-        });
-        if (!(sum > 0.0)) sc = SlotCounter{};  // identity row
-    }
-    cnt[row] = sc.slots;
-    creal[row] = sc.c;
-    diag64[row] = d;
-    wsum[row] = sum;
-    atomicMax(maxcnt, sc.c);
+__device__ inline int64_t list_base(int64_t r) {
+    return ((r / kWave) * kChunks * kWave + (r % kWave)) * kChunk;
+}
+__device__ inline int64_t list_off(int32_t k) {
+    return (int64_t)(k / kChunk) * (kWave * kChunk) + (k % kChunk);
 }
 
-// One lane per row of a slice (rows >= n write padding).  Same coefficients
-// and row sums as k_row_fill, bit for bit (same weights, same sums).
+// Row kinds: fluid rows take every neighbour, dummy-wall rows their fluid
+// neighbours, other wall rows none (identity rows).
+enum { kRowNone = 0, kRowFluid = 1, kRowDummy = 2 };
+__device__ inline int row_kind(const PartView& pv, const OpParams& op, int32_t row) {
+    if (pv.type[row] == SPH_FLUID) return kRowFluid;
+    return op.wall == SPH_WALL_DUMMY ? kRowDummy : kRowNone;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_scan(NbrView nv, PartView pv, OpParams op,
+                                                     int32_t* __restrict__ cnt, int32_t* __restrict__ creal,
+                                                     int32_t* __restrict__ list) {
+    __shared__ int32_t buf[kBlock * kBufStride];
+    const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (b >= nv.n) return;  // (each lane uses only its own LDS words)
+    const int32_t row = (int32_t)b;
+    int32_t* my = buf + threadIdx.x * kBufStride;
+    int32_t* out = list + list_base(b);
+    const auto flush = [&](int32_t q) {
+        int4* dst = reinterpret_cast<int4*>(out + (int64_t)q * (kWave * kChunk));
+#pragma unroll
+        for (int i = 0; i < kChunk / 4; ++i)
+            dst[i] = make_int4(my[4 * i], my[4 * i + 1], my[4 * i + 2], my[4 * i + 3]);
+    };
+    SlotCounter sc;
+    const auto push = [&](int32_t a) {
+        const int32_t e = sc.c % kChunk;
+        my[e] = a;
+        if (e == kChunk - 1 && sc.c < kListCap) flush(sc.c / kChunk);
+        sc.add(a);
+    };
+    const int kind = row_kind(pv, op, row);
+    if (kind == kRowFluid) {
+        for_each_neighbor(nv, row, [&](int32_t a, double) { push(a); });
+    } else if (kind == kRowDummy) {
+        for_each_neighbor(nv, row, [&](int32_t a, double) {
+            if (pv.type[a] == SPH_FLUID) push(a);
+        });
+    }
+    if (sc.c <= kListCap && sc.c % kChunk) flush(sc.c / kChunk);
+    cnt[row] = sc.slots;
+    creal[row] = sc.c;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_row_fill_staged(PartView pv, OpParams op, int64_t n,
-                                                            const int32_t* __restrict__ creal,
-                                                            const int32_t* __restrict__ stage,
-                                                            const double* __restrict__ wstage,
-                                                            const double* __restrict__ diag64,
-                                                            const double* __restrict__ wsum,
-                                                            const int64_t* __restrict__ sl_ptr, T* __restrict__ coef,
-                                                            uint16_t* __restrict__ dcol, float* __restrict__ lo,
-                                                            int32_t* __restrict__ c0, T* __restrict__ dg,
-                                                            double* __restrict__ rs64, int64_t nslices) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView pv, OpParams op, int64_t nslices,
+                                                          const int32_t* __restrict__ creal,
+                                                          const int32_t* __restrict__ list,
+                                                          double* __restrict__ wlist,
+                                                          const int64_t* __restrict__ sl_ptr, T* __restrict__ coef,
+                                                          uint16_t* __restrict__ dcol, float* __restrict__ lo,
+                                                          int32_t* __restrict__ c0, T* __restrict__ dg,
+                                                          double* __restrict__ rs64, double* __restrict__ diag64) {
+    const int64_t r = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (r >= nslices * kWave) return;
+    const Grid& g = nv.g;
     const int64_t s = r / kWave;
-    const int lane = (int)(r % kWave);
-    const bool valid = r < n;
+    const bool valid = r < nv.n;
     const int32_t row = valid ? (int32_t)r : 0;
-    const bool fluid = valid && pv.type[row] == SPH_FLUID;
-    const int32_t c = valid ? creal[row] : 0;
-    const double D = valid ? diag64[row] : 1.0;
-    const double sW = valid ? wsum[row] : 0.0;
-    const int64_t so = s * (int64_t)(kFillCap * kWave) + lane;
-    const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
-    RowWriter<T> wr{coef, dcol, lo, sl_ptr[s] + lane};
-    for (int32_t k = 0; k < c; ++k) {
-        const int32_t col = stage[so + k * kWave];
-        const double w = wstage[so + k * kWave];
-        double cf;
-        if (fluid) {
-            const double aba = -op.dt * w;
-            cf = op.jacobi ? aba / D : aba;
-        } else {
-            cf = w / sW;
+    const int kind = valid ? row_kind(pv, op, row) : kRowNone;
+    int32_t c = kind != kRowNone ? creal[row] : 0;
+    const bool listed = c <= kListCap;
+    const int32_t* lst = list + list_base(r);
+    double* wl = wlist + (r / kWave) * (kListCap * kWave) + r % kWave;  // entry k at wl[k * kWave]
+    const Pos4 pb = nv.pos[row];
+    const double mu_b = pv.mu[row], ir_b = pv.inv_rho[row];
+    const auto weight = [&](int32_t a, double r2) {
+        if (kind != kRowFluid) return pair_W(g, r2);
+        const double2 ma = pv.mu_mr[a];
+        return pair_w_v(g, op.avg, ma.x, ma.y, mu_b, ir_b, r2);
+    };
+    // r^2 exactly as the scan computes it
+    const auto dist2 = [&](int32_t a) {
+        const Pos4 pa = nv.pos[a];
+        double dx = disp(pb.x, pa.x, g.period[0]);
+        double dy = disp(pb.y, pa.y, g.period[1]);
+        double dz = disp(pb.z, pa.z, g.period[2]);
+        return (dx * dx + dy * dy) + dz * dz;
+    };
+    const auto scan = [&](auto&& f) {  // unlisted rows: the scan again
+        for_each_neighbor(nv, row, [&](int32_t a, double r2) {
+            if (kind == kRowDummy && pv.type[a] != SPH_FLUID) return;
+            f(a, r2);
+        });
+    };
+    double sum = 0.0;
+    if (listed) {
+        for (int32_t k = 0; k < c; ++k) {
+            const int32_t a = lst[list_off(k)];
+            const double w = weight(a, dist2(a));
+            wl[k * kWave] = w;
+            sum += w;
         }
-        wr.put(col, cf);
+    } else {
+        scan([&](int32_t a, double r2) { sum += weight(a, r2); });
+    }
+    const double D = kind == kRowFluid ? 1.0 + op.dt * sum : 1.0;
+    if (kind == kRowDummy && !(sum > 0.0)) c = 0;  // identity row
+    const auto coefficient = [&](double w) {
+        if (kind == kRowFluid) {
+            const double aba = -op.dt * w;
+            return op.jacobi ? aba / D : aba;
+        }
+        return w / sum;
+    };
+    const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
+    RowWriter<T> wr{coef, dcol, lo, sl_ptr[s] + r % kWave};
+    int32_t first = row;
+    if (listed) {
+        for (int32_t k = 0; k < c; ++k) {
+            const int32_t a = lst[list_off(k)];
+            if (k == 0) first = a;
+            wr.put(a, coefficient(wl[k * kWave]));
+        }
+    } else if (c > 0) {
+        scan([&](int32_t a, double r2) {
+            if (wr.j == 0) first = a;
+            wr.put(a, coefficient(weight(a, r2)));
+        });
     }
     wr.pad(width);
     if (valid) {
-        c0[row] = c > 0 ? stage[so] : row;
-        // row sums as in k_row_fill: 1/A_rr (Jacobi) or 1 on fluid rows, 2 on
-        // dummy rows with fluid neighbours, 1 on identity rows
-        const double rs = fluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
+        c0[row] = first;
+        // row sums: 1/A_rr (Jacobi) or 1 on fluid rows (eqs. diag, offdiag),
+        // 2 on dummy rows with fluid neighbours (eq. implicit-system-dummy-full),
+        // 1 on identity rows
+        const double rs = kind == kRowFluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
         dg[row] = (T)rs;
         rs64[row] = rs;
+        diag64[row] = D;
     }
 }
 
@@ -415,10 +485,10 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     const int64_t n = nb->n;
     const int64_t nslices = ceil_div(n, kWave);
     // SPH_BUILD_LEGACY=1 selects the build with the coefficients evaluated
-    // inside the scan (the reference the staged build is tested against)
+    // inside the scan (the reference the list build is tested against)
     const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
-    int32_t *cnt = nullptr, *creal = nullptr, *stage = nullptr;
-    double *d = nullptr, *ws = nullptr, *wstage = nullptr;
+    int32_t *cnt = nullptr, *creal = nullptr, *list = nullptr;
+    double *d = nullptr, *ws = nullptr, *wlist = nullptr;
     int64_t *size = nullptr, *ptr = nullptr;
     SPH_TRY(ctx->ensure_t(kCnt, n, &cnt));
     SPH_TRY(ctx->ensure_t(kCntReal, n, &creal));
@@ -428,18 +498,18 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     unsigned long long* nnz_dev = nullptr;  // [0] nonzeros, [1] longest row
     SPH_TRY(ctx->ensure_t(kNnzCount, 2, &nnz_dev));
     SPH_HIP(hipMemsetAsync(nnz_dev, 0, 2 * sizeof(unsigned long long), ctx->stream));
-    int32_t* maxc = reinterpret_cast<int32_t*>(nnz_dev + 1);
-    const dim3 rows_grid((unsigned)ceil_div(n, kBlock));
+    // row kernels: whole XCD rounds of blocks (xcd_block needs a multiple of 8)
+    const dim3 rows_grid((unsigned)(ceil_div(ceil_div(n, kBlock), kNumXcd) * kNumXcd));
+    const dim3 slice_grid((unsigned)(ceil_div(ceil_div(nslices * kWave, kBlock), kNumXcd) * kNumXcd));
     if (legacy) {
         SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
-        hipLaunchKernelGGL(k_row_count, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal, d,
-                           ws);
+        hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                           nb->view(), pv, op, cnt, creal, d, ws);
     } else {
-        SPH_TRY(ctx->ensure_t(kStage, (size_t)nslices * kFillCap * kWave, &stage));
-        SPH_TRY(ctx->ensure_t(kWStage, (size_t)nslices * kFillCap * kWave, &wstage));
-        SPH_TRY(ctx->ensure_t(kWsum, n, &ws));
-        hipLaunchKernelGGL(k_row_count_stage, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal,
-                           maxc, stage, wstage, d, ws);
+        SPH_TRY(ctx->ensure_t(kList, (size_t)nslices * kListCap * kWave, &list));
+        SPH_TRY(ctx->ensure_t(kWList, (size_t)nslices * kListCap * kWave, &wlist));
+        hipLaunchKernelGGL(k_row_scan, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal,
+                           list);
     }
     hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
                        n, nslices, cnt, creal, size, nnz_dev);
@@ -450,7 +520,6 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     SPH_HIP(hipMemcpyAsync(&nnzp, ptr + nslices, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     SPH_HIP(hipMemcpyAsync(hcnt, nnz_dev, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
     SPH_HIP(hipStreamSynchronize(ctx->stream));
-    const int32_t longest = *reinterpret_cast<const int32_t*>(&hcnt[1]);
     if (nnz_out) *nnz_out = (int64_t)hcnt[0];
     if (slots_out) *slots_out = nnzp;
     T* coef = nullptr;
@@ -466,14 +535,11 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     double* rs64 = nullptr;
     SPH_TRY(ctx->ensure_t(kDg, n, &dg));
     SPH_TRY(ctx->ensure_t(kRs64, n, &rs64));
-    if (!legacy && longest <= kFillCap) {
-        hipLaunchKernelGGL(k_row_fill_staged<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
-                           ctx->stream, pv, op, n, creal, stage, wstage, d, ws, ptr, coef, dcol, lo, c0, dg, rs64,
-                           nslices);
-        SPH_LAUNCHED("k_row_fill_staged");
+    if (!legacy) {
+        hipLaunchKernelGGL(k_row_fill_list<T>, slice_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op,
+                           nslices, creal, list, wlist, ptr, coef, dcol, lo, c0, dg, rs64, d);
+        SPH_LAUNCHED("k_row_fill_list");
     } else {
-        // (after the staged count, a row longer than the staging capacity:
-        // its diagonal and sums are already in d and ws)
         hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,
                            ctx->stream, nb->view(), pv, op, d, ws, ptr, coef, dcol, lo, c0, dg, rs64, nslices);
         SPH_LAUNCHED("k_row_fill");

@@ -119,12 +119,17 @@ __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) 
 // Pair weight w_ba = -2 mubar m_a F(r)/(rho_a rho_b) >= 0 of row b and
 // neighbour a (eq. kab, diffusive sign), from the precomputed m_a/rho_a,
 // 1/rho_b and powers of 1/h (one division left: the harmonic mean).
-__device__ inline double pair_w(const PartView& pv, const Grid& g, int avg, int32_t b,
-                                int32_t a, double r2) {
+__device__ inline double pair_w_v(const Grid& g, int avg, double mu_a, double mr_a, double mu_b, double ir_b,
+                                  double r2) {
     const double q = sqrt(r2) * g.inv_h;
     const double F = wendland_f(q) * g.inv_h5;
-    const double tm = two_mubar(pv.mu[a], pv.mu[b], avg);
-    return -(tm * pv.m_rho[a] * F) * pv.inv_rho[b];
+    const double tm = two_mubar(mu_a, mu_b, avg);
+    return -(tm * mr_a * F) * ir_b;
+}
+__device__ inline double pair_w(const PartView& pv, const Grid& g, int avg, int32_t b,
+                                int32_t a, double r2) {
+    const double2 ma = pv.mu_mr[a];
+    return pair_w_v(g, avg, ma.x, ma.y, pv.mu[b], pv.inv_rho[b], r2);
 }
 
 // Kernel value W_ba of the dummy-wall rows (eq. dummyvel).

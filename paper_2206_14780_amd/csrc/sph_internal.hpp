@@ -55,7 +55,7 @@ struct PartView {
     const double* rho;
     const double* mu;
     const uint8_t* type;
-    const double* m_rho;    // mass / rho
+    const double2* mu_mr;   // (mu, mass / rho), the neighbour data of a pair weight
     const double* inv_rho;  // 1 / rho
 };
 
@@ -170,11 +170,11 @@ Launch make_launch(int64_t n);
 // Device workspace: named, monotonically growing allocations of a context.
 // ---------------------------------------------------------------------------
 enum Slot : int {
-    kMass, kRho, kMu, kType, kMRho, kInvRho, kCnt, kCntReal, kDiag64, kWsum, kSlSize, kSlPtr, kCoef, kDcol, kC0, kDg, kLo, kRs64,
+    kMass, kRho, kMu, kType, kMuMr, kInvRho, kCnt, kCntReal, kDiag64, kWsum, kSlSize, kSlPtr, kCoef, kDcol, kC0, kDg, kLo, kRs64,
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,
-    kWarmPart2, kWarmU, kStage, kWStage, kNumSlots
+    kWarmPart2, kWarmU, kList, kWList, kNumSlots
 };
 
 }  // namespace sph

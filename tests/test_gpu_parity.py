@@ -2,6 +2,8 @@
 the same seeded inputs.  Neighbour lists bit-exact; operator within a
 rounding bound derived from the arithmetic; solutions within 1e-10 (FP64
 path) and 1e-5 (FP32 path) relative L2."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -274,13 +276,20 @@ def test_restart_on_drop_matches_oracle_fp64(ctx):
 @pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_F32])
 @pytest.mark.parametrize("wall", [W.WALL_DYNAMIC, W.WALL_DUMMY])
 @pytest.mark.parametrize("jacobi", [True, False])
-def test_staged_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, monkeypatch):
-    # the LDS-staged build must reproduce the two-kernel build bit for bit:
-    # same pairs, same summation order, same coefficients and row sums
-    for w in (small_tank(seed=61, wall=wall), W.open_box(14, wall=wall)):
+def test_list_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, monkeypatch):
+    # The list build (neighbour lists from the scan, weights evaluated in
+    # list order by the fill) must reproduce the two-kernel build bit for
+    # bit: same pairs, same summation order, same coefficients and row sums.
+    # The channels have periodic axes of 1 and 2 cells; in the wide-kernel
+    # tank (h = 1.5 dp, ~113 neighbours) most rows exceed the 96-entry list
+    # and are rescanned by the fill.
+    wide = dataclasses.replace(small_tank(seed=65, n=(10, 10, 6), wall=wall), h=1.5)
+    cases = (small_tank(seed=61, wall=wall), W.open_box(14, wall=wall),
+             W.poiseuille(4, wall=wall, shuffle_seed=63), W.poiseuille(6, wall=wall, shuffle_seed=64), wide)
+    for w in cases:
+        print(f"[build] {w.name} h={w.h} prec={prec} jacobi={jacobi}", flush=True)
         g = GpuCase(ctx, w)
         X = np.random.default_rng(62).normal(size=(w.n, 3))
-        print(f"[build] {w.name} prec={prec} jacobi={jacobi}", flush=True)
         y_new = g.apply(X, prec, jacobi=jacobi)
         Xs, rs = g.solve(w.rhs, prec, tol=1e-6)
         monkeypatch.setenv("SPH_BUILD_LEGACY", "1")
@@ -290,6 +299,8 @@ def test_staged_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, m
         assert np.array_equal(y_new, y_old)
         assert rs["mat_nnz"] == rl["mat_nnz"] and rs["mat_slots"] == rl["mat_slots"]
         assert rs["history"] == rl["history"] and np.array_equal(Xs, Xl)
+        if w is wide:
+            assert rs["mat_nnz"] > 96 * (w.ptype == W.FLUID).sum()  # every fluid row has 98+
 
 
 def _wide_slab():
