@@ -45,6 +45,9 @@ def lib():
         L.orc_neighbors_grid.restype = C.c_int64
         L.orc_neighbors_grid.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_double, i64p, i32p,
                                          C.c_int64]
+        L.orc_neighbors_grid_rows.restype = C.c_int64
+        L.orc_neighbors_grid_rows.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_double, i64p, C.c_int64,
+                                              i64p, i32p, C.c_int64]
         L.orc_apply.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.POINTER(dp)]
         L.orc_diag.argtypes = [C.POINTER(OrcOp), dp]
         L.orc_assemble_dense.argtypes = [C.POINTER(OrcOp), dp]
@@ -128,6 +131,32 @@ def neighbors(pos, period, h, lo=None, method="grid"):
                  cols.ctypes.data_as(C.POINTER(C.c_int32)), cap]
         fn = L.orc_neighbors_grid if method == "grid" else L.orc_neighbors_brute
         nnz = int(fn(*args))
+        if nnz <= cap:
+            return row_ptr, cols[:nnz].copy()
+        cap = nnz
+
+
+def neighbors_rows(pos, period, h, rows, lo=None):
+    """CSR lists (row_ptr int64 [n+1], cols int32 ascending) holding the
+    neighbour set of `rows` only (every other row empty): the cell-grid search
+    of `neighbors` restricted to a sample of rows, so that an Operator built
+    on it gives exact rows of A for systems too large for full lists."""
+    L = lib()
+    x, y, z = _soa(pos)
+    n = x.shape[0]
+    rows = np.unique(np.asarray(rows, dtype=np.int64))
+    if rows.size and (rows[0] < 0 or rows[-1] >= n):
+        raise ValueError("row out of range")
+    per = np.ascontiguousarray(np.asarray(period, dtype=np.float64))
+    lo_ = np.ascontiguousarray(np.zeros(3) if lo is None else np.asarray(lo, dtype=np.float64))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    cap = max(1, rows.size * 128)
+    while True:
+        cols = np.zeros(cap, dtype=np.int32)
+        nnz = int(L.orc_neighbors_grid_rows(n, _dp(x), _dp(y), _dp(z), _dp(lo_), _dp(per), float(h),
+                                            rows.ctypes.data_as(C.POINTER(C.c_int64)), rows.size,
+                                            row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            cols.ctypes.data_as(C.POINTER(C.c_int32)), cap))
         if nnz <= cap:
             return row_ptr, cols[:nnz].copy()
         cap = nnz

@@ -315,6 +315,55 @@ int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y, const do
     return nnz;
 }
 
+/* Neighbour lists of the listed rows only (every other row gets an empty
+ * list): the cell-grid search and predicate of orc_neighbors_grid, for checks
+ * of single rows of systems too large for full lists.  rows[] ascending and
+ * distinct, each in [0, n); row_ptr has n + 1 entries. */
+int64_t orc_neighbors_grid_rows(int64_t n, const double *x, const double *y, const double *z,
+                                const double *lo, const double *period, double h,
+                                const int64_t *rows, int64_t nrows, int64_t *row_ptr,
+                                int32_t *cols, int64_t cap) {
+    orc_grid g;
+    orc_grid_build(&g, n, x, y, z, lo, period, h);
+    double s = 2.0 * h;
+    double cut2 = s * s;
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k];
+        int64_t st[27];
+        int m = orc_grid_stencil(&g, g.cell_of[i], period, st);
+        int64_t c = 0;
+        for (int q = 0; q < m; ++q)
+            for (int64_t t = g.start[st[q]]; t < g.start[st[q] + 1]; ++t) {
+                int64_t j = g.items[t];
+                if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) ++c;
+            }
+        cnt[i] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    int64_t nnz = row_ptr[n];
+    if (nnz <= cap) {
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = 0; k < nrows; ++k) {
+            int64_t i = rows[k];
+            int64_t st[27];
+            int m = orc_grid_stencil(&g, g.cell_of[i], period, st);
+            int64_t k0 = row_ptr[i], kk = k0;
+            for (int q = 0; q < m; ++q)
+                for (int64_t t = g.start[st[q]]; t < g.start[st[q] + 1]; ++t) {
+                    int64_t j = g.items[t];
+                    if (j != i && orc_dist2(x, y, z, i, j, period, 0, 0, 0) < cut2) cols[kk++] = (int32_t)j;
+                }
+            qsort(cols + k0, (size_t)(kk - k0), sizeof(int32_t), orc_cmp_i32);
+        }
+    }
+    free(cnt);
+    orc_grid_free(&g);
+    return nnz;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The viscous matrix A(dt) (Section "From explicit to semi-implicit").       */
 /* ------------------------------------------------------------------------ */

@@ -101,3 +101,31 @@ def test_neighbours_minimum_image_by_hand():
     for method in ("brute", "grid"):
         rp, cols = O.neighbors(pos, [10.0, 0.0, 0.0], 0.5, lo=[0, 0, 0], method=method)
         assert rp.tolist() == [0, 1, 2, 2] and cols.tolist() == [1, 0]
+
+
+@pytest.mark.parametrize("seed,periodic", [(6, (1, 1, 0)), (7, (0, 0, 0)), (8, (1, 0, 1))])
+def test_row_sample_lists_equal_the_full_lists(seed, periodic):
+    # The row-restricted search (used to check single rows of very large
+    # systems) returns exactly the brute-force lists on the sampled rows and
+    # nothing elsewhere, and an operator built on it reproduces those rows of
+    # A X bit for bit.
+    pos, pt, lo, period, h = _random_system(seed, periodic=periodic)
+    n = pos.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(n, size=n // 7, replace=False))
+    rp_b, cols_b = O.neighbors(pos, period, h, method="brute")
+    rp_s, cols_s = O.neighbors_rows(pos, period, h, rows[::-1], lo=lo)  # any order in
+    cnt_s = np.diff(rp_s)
+    sampled = np.zeros(n, dtype=bool)
+    sampled[rows] = True
+    assert np.all(cnt_s[~sampled] == 0)
+    for i in rows:
+        assert np.array_equal(cols_s[rp_s[i]:rp_s[i + 1]], cols_b[rp_b[i]:rp_b[i + 1]])
+    mu = 10.0 ** rng.uniform(0.0, 2.0, n)
+    X = rng.normal(size=(n, 3))
+    for wall in (W.WALL_DYNAMIC, W.WALL_DUMMY):
+        kw = dict(pos=pos, mass=np.ones(n), rho=np.ones(n), mu=mu, ptype=pt, period=period, h=h,
+                  dt=0.5, wall=wall, avg=W.AVG_HARMONIC, lo=lo)
+        full = O.Operator(nbr=(rp_b, cols_b), **kw).apply(X)
+        part = O.Operator(nbr=(rp_s, cols_s), **kw).apply(X)
+        assert np.array_equal(full[rows], part[rows])
