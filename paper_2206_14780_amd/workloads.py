@@ -269,6 +269,15 @@ def lava_channel(n=320, seed=5, nu0=1e4, b=0.02, T_lo=1000.0, T_hi=1200.0,
                     meta=dict(dp=1.0, seed=seed))
 
 
+def next_step_rhs(w: Workload, V) -> np.ndarray:
+    """Right-hand side of the next implicit step of a sequence started from
+    rest, V_k = A^-1 (V_{k-1} + f): the previous solution plus the per-step
+    forcing f = the first step's rhs (taken with V_0 = 0) on fluid rows, 0 on
+    wall rows."""
+    fl = (w.ptype == FLUID)[:, None]
+    return np.where(fl, np.asarray(V, dtype=np.float64) + w.rhs, 0.0)
+
+
 def with_random_order(w: Workload, seed: int) -> Workload:
     """Same system with the particles listed in a seeded random order."""
     rng = np.random.default_rng(seed)
