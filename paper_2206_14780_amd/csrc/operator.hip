@@ -569,7 +569,7 @@ Launch make_launch(int64_t n) {
     L.n = n;
     const int64_t nslices = ceil_div(n, kWave);
     int32_t ba = env_int("SPH_APPLY_BLOCK", 256);
-    ba = std::min(std::max(ba / kWave * kWave, kWave), kMaxBlock);
+    ba = std::min(std::max(ba / kWave * kWave, kWave), kApplyMaxBlock);
     const int64_t wpb = ba / kWave;
     // one 64-row slice per wave: the launch's tail is then one slice long
     // (measured fastest for whole iterations on the 1.16M and 4.49M tanks);

@@ -52,19 +52,27 @@ __device__ inline double sell_lo(const Sell<double>&, int64_t) { return 0.0; }
 __device__ inline int32_t jump_bits(float w) { return __float_as_int(w); }
 __device__ inline int32_t jump_bits(double w) { return (int32_t)__double_as_longlong(w); }
 
-constexpr int kGroup = 8;  // entries per software-pipelined group
+// Entries per software-pipelined group: 16 for the FP32 operator (more
+// loads in flight), 8 where FP64 values or the FP64-accurate residual would
+// not fit the registers.
+template <typename T, bool RES>
+constexpr int group_of() { return sizeof(T) == 4 && !RES ? 16 : 8; }
 
 // Raw slots of one group (zero beyond the row's width).
 template <typename T, bool RES>
-__device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width, int32_t k0, T (&w)[kGroup],
-                                  uint16_t (&d)[kGroup], double (&l)[kGroup]) {
+__device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width, int32_t k0,
+                                  T (&w)[group_of<T, RES>()], uint16_t (&d)[group_of<T, RES>()],
+                                  double (&l)[group_of<T, RES>()]) {
+    constexpr int kGroup = group_of<T, RES>();
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
         const int32_t k = k0 + u;
         if (k < width) {
             const int64_t i = base + (int64_t)k * kWave;
-            w[u] = A.coef[i];
-            d[u] = A.dcol[i];
+            // read once per launch: non-temporal, so the stream does not
+            // evict the x values that the gathers reuse from L2
+            w[u] = __builtin_nontemporal_load(A.coef + i);
+            d[u] = __builtin_nontemporal_load(A.dcol + i);
             l[u] = RES ? sell_lo(A, i) : 0.0;
         } else {
             w[u] = T(0);
@@ -87,6 +95,7 @@ __device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width,
 template <typename T, bool RES, typename ACC, typename XT = T>
 __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, int32_t row,
                                 const XT* __restrict__ x, const V3<XT>& xs, ACC& a0, ACC& a1, ACC& a2) {
+    constexpr int kGroup = group_of<T, RES>();
     int32_t col = A.c0[row];
     T rw[kGroup];
     uint16_t rd[kGroup];
@@ -130,7 +139,7 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
 // the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead, and
 // x may be held in another precision XT.
 template <typename T, int MODE, typename XT = T>
-__global__ __launch_bounds__(kMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
+__global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
                                                           const XT* __restrict__ x, T* __restrict__ y,
                                                           const T* __restrict__ w, const double* __restrict__ b64,
                                                           double* __restrict__ part) {
@@ -236,7 +245,7 @@ __device__ inline void row_apply_otf(const NbrView& nv, const PartView& pv, cons
 // y = b64 - A x instead (FP64 residual rounded to T) and its squared norm,
 // x then being of precision XT.
 template <typename T, int MODE, typename XT = T>
-__global__ __launch_bounds__(kMaxBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
+__global__ __launch_bounds__(kApplyMaxBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
                                                          OpParams op, const XT* __restrict__ x, T* __restrict__ y,
                                                          const T* __restrict__ w, const double* __restrict__ b64,
                                                          double* __restrict__ part) {

@@ -16,6 +16,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per block of the simple per-particle kernels
 constexpr int kMaxBlock = 1024;    // largest block of the row kernels
 constexpr int kMaxWaves = kMaxBlock / kWave;
+constexpr int kApplyMaxBlock = 256;  // largest block of the operator kernels (register budget)
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
 constexpr double kPi = 3.14159265358979323846;
 
@@ -159,7 +160,7 @@ struct SolveConst {
 struct Launch {
     int64_t n;
     int32_t grid_apply;    // blocks of the operator kernels
-    int32_t block_apply;   // threads per operator block (multiple of 64, <= kMaxBlock)
+    int32_t block_apply;   // threads per operator block (multiple of 64, <= kApplyMaxBlock)
     int32_t grid_stream;   // blocks of the streaming kernels
     int32_t block_stream;  // threads per streaming block
 };
