@@ -118,9 +118,12 @@ typedef struct {
  *          flag (0 = library default).  Does not change the result.
  *   force_stall_iter / force_stall_comp: test hook; at that iteration that
  *          component's delta is treated as zero.  -1 = off.
- *   profile: 1 = bracket every executed launch of the second operator kernel
- *          of an iteration (A r_star and its dot products) with HIP events on
- *          the context stream and report their total time (apply_ms).
+ *   profile: k > 0 = bracket the second operator launch (A r_star and its
+ *          dot products) of every k-th iteration with HIP events on the
+ *          context stream and report the total time of the executed ones
+ *          (apply_ms, apply_launches); 0 = off.  Each event pair leaves a
+ *          gap of a few microseconds in the stream, so k > 1 keeps the
+ *          measurement from slowing the solve it measures.
  *   restart_drop: at each periodic true-residual check, a progressing
  *          component whose true r.r has fallen below restart_drop times its
  *          r.r at the last (re)start restarts from the true residual

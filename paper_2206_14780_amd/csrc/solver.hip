@@ -516,7 +516,7 @@ struct Solver {
     SolveConst sc;
     int32_t launches = 0;
     // profiling of the A r_star launches: (iteration, issue round, event pair)
-    bool profile = false;
+    int32_t profile = 0;  // time the A r_star launch of every profile-th iteration
     int32_t round = 0;
     struct Rec {
         int32_t it, round, ev;
@@ -559,7 +559,8 @@ struct Solver {
         apply<kDotA1>(halt, p, ap, rh0, pa1);
         hipLaunchKernelGGL(k_supd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pa1, L.grid_apply, L.n, r, ap, s);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (profile) {
+        const bool timed = profile > 0 && it % profile == 0;
+        if (timed) {
             const int k = (int)recs.size();
             SPH_TRY(prof_event(2 * k, &ev0));
             SPH_TRY(prof_event(2 * k + 1, &ev1));
@@ -568,12 +569,12 @@ struct Solver {
         }
         if (sc.variant == SPH_STANDARD) {
             apply<kDotA2Std>(halt, s, as, nullptr, pa2);
-            if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
+            if (timed) SPH_HIP(hipEventRecord(ev1, ctx->stream));
             hipLaunchKernelGGL((k_close<T, 9, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
                                p, s, as, r, rh0, pk3);
         } else {
             apply<kDotA2>(halt, s, as, nullptr, pa2);
-            if (profile) SPH_HIP(hipEventRecord(ev1, ctx->stream));
+            if (timed) SPH_HIP(hipEventRecord(ev1, ctx->stream));
             hipLaunchKernelGGL((k_close<T, 6, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
                                p, s, as, r, rh0, pk3);
         }
@@ -614,7 +615,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
 
     SPH_TRY(gather_props(ctx, nb, part, &S.pv));
     ++S.launches;
-    S.profile = o->profile != 0;
+    S.profile = std::max(o->profile, 0);
     if (S.mode == SPH_OP_CACHED) {
         SPH_TRY(build_sell<T>(ctx, nb, S.pv, S.op, &S.sell, &S.diag64, &rep->mat_nnz, &rep->mat_slots));
         S.launches += 6;
@@ -826,7 +827,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     rep->setup_ms = ms_setup;
     rep->iterate_ms = ms_iter;
     rep->launches = S.launches;
-    if (S.profile) {
+    if (S.profile > 0) {
         double tot = 0.0;
         int32_t cnt = 0;
         for (const auto& rc : S.recs) {

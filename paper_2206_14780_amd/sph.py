@@ -178,7 +178,7 @@ def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res
     fi, fc = force_stall if force_stall is not None else (-1, -1)
     o = sph_solve_opts(float(tol), int(max_iter), int(variant), float(floor),
                        int(true_res_period), int(bool(x0_given)), int(poll_every), int(fi), int(fc),
-                       int(bool(profile)), float(restart_drop))
+                       int(profile), float(restart_drop))
     if warm_params is not None:
         o.warm_params = _ptr(warm_params)
         if warm_u is not None:
