@@ -188,32 +188,134 @@ __device__ inline void load_tile(Tile& T, const float* __restrict__ S, const int
     }
 }
 
-// Forward only: out[s] = (o0, o1, o2, pred) for samples [0, n).
-__global__ __launch_bounds__(kThreads) void k_mlp_forward(const float* __restrict__ S, int64_t n,
-                                                          const float* __restrict__ params,
-                                                          float* __restrict__ out, int32_t tiles_per_wave) {
-    __shared__ Smem sm;
-    load_params(sm, params);
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, g = lane / 16, c = lane % 16;
-    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
-    for (int q = 0; q < tiles_per_wave; ++q) {
-        const int64_t base = (gw * tiles_per_wave + q) * 16;
-        Tile T;
-        load_tile(T, S, nullptr, base, n - base, g, c);
-        tile_forward(sm, T, wave, g, c);
-        if (lane < 16 && base + lane < n) {
-            const float* o = &sm.go[wave][lane * 4];
-            const float* ps = S + (base + lane) * kSample;
-            float pred = o[0] * ps[4];
-            pred = __builtin_fmaf(o[1], ps[5], pred);
-            pred = __builtin_fmaf(o[2], ps[6], pred);
-            float* w = out + (base + lane) * 4;
-            w[0] = o[0];
-            w[1] = o[1];
-            w[2] = o[2];
-            w[3] = pred;
+// Inference: out[s] = (o0, o1, o2, pred) for samples [0, n).  The products
+// run transposed, Z^T = W^T H^T, with the 16 samples of a tile on the MFMA N
+// dimension: a product's output then sits in registers exactly as the next
+// product's B operand (lane (g, c) holds features 16t + 4g + r of sample c),
+// so no LDS transpose is needed, and the weights, as A operands, stay in
+// registers for the whole launch.  Same roundings as the training kernel's
+// forward pass (BF16 weights and layer inputs of the 64x64 products, FP32
+// layers 1 and 4); only the order of the FP32 sums differs.
+// Two floats to packed BF16, nearest-even (the hardware conversion of
+// gfx950; the same rounding as f2bf on finite values).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 hbf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pk_bf16(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, hbf16x2));
+}
+__device__ inline bf16x4 bf16x4_of(float v0, float v1, float v2, float v3) {
+    return __builtin_bit_cast(bf16x4, u32x2{pk_bf16(v0, v1), pk_bf16(v2, v3)});
+}
+
+struct alignas(16) InferSmem {
+    alignas(16) float w1[kIn][kH];  // BF16-rounded values
+    alignas(16) float b1[kH];
+    alignas(16) float b2[kH];
+    alignas(16) float b3[kH];
+    alignas(16) float w4[kH][4];    // BF16-rounded values, padded to 4
+    alignas(16) float b4[4];
+};
+
+__global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict__ S, int64_t n,
+                                                        const float* __restrict__ p, float* __restrict__ out) {
+    __shared__ __align__(16) InferSmem sm;
+    for (int i = threadIdx.x; i < kIn * kH; i += blockDim.x) sm.w1[i / kH][i % kH] = rbf(p[kOW1 + i]);
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        sm.b1[i] = p[kOB1 + i];
+        sm.b2[i] = p[kOB2 + i];
+        sm.b3[i] = p[kOB3 + i];
+        for (int k = 0; k < 4; ++k) sm.w4[i][k] = k < kOut ? rbf(p[kOW4 + i * kOut + k]) : 0.f;
+    }
+    if (threadIdx.x < 4) sm.b4[threadIdx.x] = threadIdx.x < kOut ? p[kOB4 + threadIdx.x] : 0.f;
+    // A operands: a[t][s] holds W[16s + 4g + r][16t + c] (W stored [in][out])
+    const int lane = threadIdx.x % kWave, g = lane / 16, c = lane % 16;
+    bf16x4 a2[4][4], a3[4][4];
+    for (int t = 0; t < 4; ++t)
+        for (int s = 0; s < 4; ++s)
+            for (int r = 0; r < 4; ++r) {
+                const int in = 16 * s + 4 * g + r, o = 16 * t + c;
+                a2[t][s][r] = (short)f2bf(p[kOW2 + in * kH + o]);
+                a3[t][s][r] = (short)f2bf(p[kOW3 + in * kH + o]);
+            }
+    __syncthreads();
+    const int64_t ntiles = ceil_div(n, (int64_t)16);
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; tile < ntiles; tile += nw) {
+        // re-read the small LDS tables every tile rather than keeping them
+        // in registers (which would leave room for one wave per SIMD)
+        __asm__ volatile("" ::: "memory");
+        const int64_t smp = tile * 16 + c;
+        const bool valid = smp < n;
+        const float4 x = valid ? *reinterpret_cast<const float4*>(S + smp * kSample) : float4{0.f, 0.f, 0.f, 0.f};
+        // layer 1 (FP32), ReLU, BF16: the B operand of layer 2
+        bf16x4 h[4];
+        for (int s = 0; s < 4; ++s) {
+            const int j = 16 * s + 4 * g;
+            const float4 b = *reinterpret_cast<const float4*>(&sm.b1[j]);
+            const float4 w0 = *reinterpret_cast<const float4*>(&sm.w1[0][j]);
+            const float4 w1 = *reinterpret_cast<const float4*>(&sm.w1[1][j]);
+            const float4 w2 = *reinterpret_cast<const float4*>(&sm.w1[2][j]);
+            const float4 w3 = *reinterpret_cast<const float4*>(&sm.w1[3][j]);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+            const float c0[4] = {w0.x, w0.y, w0.z, w0.w}, c1[4] = {w1.x, w1.y, w1.z, w1.w};
+            const float c2[4] = {w2.x, w2.y, w2.z, w2.w}, c3[4] = {w3.x, w3.y, w3.z, w3.w};
+            float z[4];
+            for (int r = 0; r < 4; ++r) {
+                z[r] = bb[r];
+                z[r] = __builtin_fmaf(x.x, c0[r], z[r]);
+                z[r] = __builtin_fmaf(x.y, c1[r], z[r]);
+                z[r] = __builtin_fmaf(x.z, c2[r], z[r]);
+                z[r] = __builtin_fmaf(x.w, c3[r], z[r]);
+            }
+            h[s] = bf16x4_of(fmaxf(z[0], 0.f), fmaxf(z[1], 0.f), fmaxf(z[2], 0.f), fmaxf(z[3], 0.f));
         }
-        wave_sync();
+        // layer 2 on MFMA, bias, ReLU, BF16: the B operand of layer 3
+        f32x4 acc[4];
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[t][s], h[s], acc[t], 0, 0, 0);
+        }
+        for (int t = 0; t < 4; ++t) {
+            const float4 b = *reinterpret_cast<const float4*>(&sm.b2[16 * t + 4 * g]);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+            h[t] = bf16x4_of(fmaxf(acc[t][0] + bb[0], 0.f), fmaxf(acc[t][1] + bb[1], 0.f),
+                             fmaxf(acc[t][2] + bb[2], 0.f), fmaxf(acc[t][3] + bb[3], 0.f));
+        }
+        // layer 3 on MFMA, bias, ReLU; layer 4 (FP32) partial sums over this
+        // lane's 16 features, then over the four lane groups of the sample
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[t][s], h[s], acc[t], 0, 0, 0);
+        }
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+        for (int t = 0; t < 4; ++t) {
+            const float4 b = *reinterpret_cast<const float4*>(&sm.b3[16 * t + 4 * g]);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+            for (int r = 0; r < 4; ++r) {
+                const float v = fmaxf(acc[t][r] + bb[r], 0.f);
+                const float4 w = *reinterpret_cast<const float4*>(&sm.w4[16 * t + 4 * g + r][0]);
+                o0 = __builtin_fmaf(v, w.x, o0);
+                o1 = __builtin_fmaf(v, w.y, o1);
+                o2 = __builtin_fmaf(v, w.z, o2);
+            }
+        }
+        o0 += __shfl_xor(o0, 16, kWave);
+        o1 += __shfl_xor(o1, 16, kWave);
+        o2 += __shfl_xor(o2, 16, kWave);
+        o0 += __shfl_xor(o0, 32, kWave);
+        o1 += __shfl_xor(o1, 32, kWave);
+        o2 += __shfl_xor(o2, 32, kWave);
+        if (g == 0 && valid) {
+            o0 += sm.b4[0];
+            o1 += sm.b4[1];
+            o2 += sm.b4[2];
+            const float4 bs = *reinterpret_cast<const float4*>(S + smp * kSample + 4);
+            float pred = o0 * bs.x;
+            pred = __builtin_fmaf(o1, bs.y, pred);
+            pred = __builtin_fmaf(o2, bs.z, pred);
+            *reinterpret_cast<float4*>(out + smp * 4) = float4{o0, o1, o2, pred};
+        }
     }
 }
 
@@ -399,10 +501,11 @@ static int32_t tiles_per_wave(int64_t n, int32_t* grid) {
 
 sph_status sph::mlp::forward(sph_ctx* ctx, const float* samples, int64_t n, const float* params, float* out) {
     if (n == 0) return SPH_OK;
-    int32_t grid = 0;
-    const int32_t tpw = tiles_per_wave(n, &grid);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kThreads), 0, ctx->stream, samples, n, params, out, tpw);
-    SPH_LAUNCHED("k_mlp_forward");
+    // several tiles per wave: each wave loads its 32 weight fragments once
+    const int64_t waves = std::min<int64_t>(ceil_div(ceil_div(n, (int64_t)16), 4), 8192);
+    const int32_t grid = (int32_t)std::max<int64_t>(ceil_div(waves, (int64_t)kWaves), 1);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(kThreads), 0, ctx->stream, samples, n, params, out);
+    SPH_LAUNCHED("k_mlp_infer");
     return SPH_OK;
 }
 
