@@ -44,9 +44,6 @@ __device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V
     }
 }
 
-// Low part of an FP32 coefficient (c64 - (double)hi); FP64 matrices are exact.
-__device__ inline double sell_lo(const Sell<float>& A, int64_t i) { return (double)A.lo[i]; }
-__device__ inline double sell_lo(const Sell<double>&, int64_t) { return 0.0; }
 
 // Column jump held in the coefficient bits of an escape slot.
 __device__ inline int32_t jump_bits(float w) { return __float_as_int(w); }
@@ -58,26 +55,52 @@ __device__ inline int32_t jump_bits(double w) { return (int32_t)__double_as_long
 template <typename T, bool RES>
 constexpr int group_of() { return sizeof(T) == 4 && !RES ? 16 : 8; }
 
-// Raw slots of one group (zero beyond the row's width).
+// Raw slots of one group (zero beyond the row's width): a lane's kPack
+// adjacent slots come in one vector load each for the coefficients, the
+// column steps and (residual) the low parts.  Widths and groups are
+// multiples of kPack, so a pack is either wholly inside the row or beyond it.
+template <typename T>
+struct Pack {
+    typedef T v __attribute__((ext_vector_type(kPack)));
+};
+typedef uint16_t u16pack __attribute__((ext_vector_type(kPack)));
+
 template <typename T, bool RES>
 __device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width, int32_t k0,
                                   T (&w)[group_of<T, RES>()], uint16_t (&d)[group_of<T, RES>()],
                                   double (&l)[group_of<T, RES>()]) {
     constexpr int kGroup = group_of<T, RES>();
+    static_assert(kGroup % kPack == 0, "whole packs per group");
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-        const int32_t k = k0 + u;
+    for (int q = 0; q < kGroup / kPack; ++q) {
+        const int32_t k = k0 + q * kPack;
         if (k < width) {
-            const int64_t i = base + (int64_t)k * kWave;
+            const int64_t i = slot_of(base, k);
             // read once per launch: non-temporal, so the stream does not
             // evict the x values that the gathers reuse from L2
-            w[u] = __builtin_nontemporal_load(A.coef + i);
-            d[u] = __builtin_nontemporal_load(A.dcol + i);
-            l[u] = RES ? sell_lo(A, i) : 0.0;
+            const typename Pack<T>::v wv =
+                __builtin_nontemporal_load(reinterpret_cast<const typename Pack<T>::v*>(A.coef + i));
+            const u16pack dv = __builtin_nontemporal_load(reinterpret_cast<const u16pack*>(A.dcol + i));
+#pragma unroll
+            for (int e = 0; e < kPack; ++e) {
+                w[q * kPack + e] = wv[e];
+                d[q * kPack + e] = dv[e];
+            }
+            if constexpr (RES && sizeof(T) == 4) {
+                const typename Pack<float>::v lv = *reinterpret_cast<const typename Pack<float>::v*>(A.lo + i);
+#pragma unroll
+                for (int e = 0; e < kPack; ++e) l[q * kPack + e] = (double)lv[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < kPack; ++e) l[q * kPack + e] = 0.0;
+            }
         } else {
-            w[u] = T(0);
-            d[u] = 0;
-            l[u] = 0.0;
+#pragma unroll
+            for (int e = 0; e < kPack; ++e) {
+                w[q * kPack + e] = T(0);
+                d[q * kPack + e] = 0;
+                l[q * kPack + e] = 0.0;
+            }
         }
     }
 }
@@ -160,7 +183,7 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __
     for (int64_t s = s0 + wid; s < s1; s += nw) {
         const int64_t row = s * kWave + lane;
         if (row >= n) continue;
-        const int64_t base = A.sl_ptr[s] + lane;
+        const int64_t base = lane_base(A.sl_ptr[s], lane);
         const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
         const V3<XT> xs = ld3(x, row);
         if constexpr (RES) {

@@ -68,7 +68,11 @@ struct OpParams {
 };
 
 // Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).
-// Entry k of row r = s*64 + l lives at slot sl_ptr[s] + k*64 + l.  Columns
+// Entry k of row r = s*64 + l lives at slot
+//   sl_ptr[s] + (k / kPack) * 64 kPack + l kPack + k % kPack,
+// i.e. each lane's kPack consecutive entries are adjacent (one vector load)
+// and the 64 lanes' packs of one slot group are contiguous; slice widths are
+// multiples of kPack.  Columns
 // are delta coded: a row's columns ascend; the row starts at column c0[r]
 // and each slot adds its 16-bit step dcol (the first entry steps by 0).  A
 // step that does not fit takes an escape slot (dcol = kEscape) whose
@@ -82,6 +86,13 @@ struct OpParams {
 // lo = coefficient - (double)coef, so coef + lo carries ~48 bits for the
 // FP64-accurate residual.
 constexpr uint16_t kEscape = 0xFFFF;
+constexpr int kPack = 4;
+
+// First slot of lane l of a slice starting at slot sl, and its k-th slot.
+__host__ __device__ inline int64_t lane_base(int64_t sl, int64_t lane) { return sl + lane * kPack; }
+__host__ __device__ inline int64_t slot_of(int64_t lbase, int32_t k) {
+    return lbase + (int64_t)(k / kPack) * (64 * kPack) + k % kPack;
+}
 
 template <typename T>
 struct Sell {
