@@ -281,29 +281,38 @@ extern "C" sph_status sph_build_neighbors(sph_ctx* ctx, const sph_particles* p, 
     nb->n = n;
     nb->ncell = ncell;
     nb->g = g;
+    // temporaries from the context's workspace; the handle's arrays in one
+    // allocation (device allocations and frees cost tens of microseconds each)
     int32_t *cell = nullptr, *count = nullptr, *fill = nullptr;
-    auto cleanup = [&]() {
-        (void)hipFree(cell);
-        (void)hipFree(count);
-        (void)hipFree(fill);
-    };
     auto fail_oom = [&]() {
-        cleanup();
         sph_neighbors_free(nb);
         return ctx->fail(SPH_E_OOM, "build_neighbors: device allocation failed");
     };
-    if (hipMalloc(&nb->cell_start, sizeof(int32_t) * (ncell + 1)) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->scell, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->perm, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->iperm, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&nb->pos, sizeof(Pos4) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&cell, sizeof(int32_t) * n) != hipSuccess) return fail_oom();
-    if (hipMalloc(&count, sizeof(int32_t) * ncell) != hipSuccess) return fail_oom();
-    if (hipMalloc(&fill, sizeof(int32_t) * ncell) != hipSuccess) return fail_oom();
+    {
+        const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t b_cs = up(sizeof(int32_t) * (size_t)(ncell + 1)), b_i = up(sizeof(int32_t) * (size_t)n);
+        const size_t b_pos = up(sizeof(Pos4) * (size_t)n);
+        char* base = nullptr;
+        if (hipMalloc(&base, b_cs + 3 * b_i + b_pos) != hipSuccess) return fail_oom();
+        nb->blob = base;
+        nb->cell_start = reinterpret_cast<int32_t*>(base);
+        nb->scell = reinterpret_cast<int32_t*>(base + b_cs);
+        nb->perm = reinterpret_cast<int32_t*>(base + b_cs + b_i);
+        nb->iperm = reinterpret_cast<int32_t*>(base + b_cs + 2 * b_i);
+        nb->pos = reinterpret_cast<Pos4*>(base + b_cs + 3 * b_i);
+    }
+    {
+        sph_status st = ctx->ensure_t(kNbrCell, (size_t)n, &cell);
+        if (st == SPH_OK) st = ctx->ensure_t(kNbrCount, (size_t)ncell, &count);
+        if (st == SPH_OK) st = ctx->ensure_t(kNbrFill, (size_t)ncell, &fill);
+        if (st != SPH_OK) {
+            sph_neighbors_free(nb);
+            return st;
+        }
+    }
 
     hipError_t e = hipSuccess;
     auto hip_err = [&](const char* what) {
-        cleanup();
         sph_neighbors_free(nb);
         return ctx->hip_fail(e, what);
     };
@@ -315,7 +324,6 @@ extern "C" sph_status sph_build_neighbors(sph_ctx* ctx, const sph_particles* p, 
     if ((e = hipGetLastError()) != hipSuccess) return hip_err("k_cell_of");
     sph_status st = scan_i32(ctx, count, nb->cell_start, ncell);
     if (st != SPH_OK) {
-        cleanup();
         sph_neighbors_free(nb);
         return st;
     }
@@ -325,7 +333,6 @@ extern "C" sph_status sph_build_neighbors(sph_ctx* ctx, const sph_particles* p, 
                        p->z, nb->pos, nb->scell, nb->iperm);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err("neighbour build kernels");
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_err("hipStreamSynchronize");
-    cleanup();
     *out = nb;
     return SPH_OK;
 }
@@ -383,11 +390,7 @@ extern "C" sph_status sph_neighbors_export(sph_ctx* ctx, const sph_nbr* nb, int6
 
 extern "C" sph_status sph_neighbors_free(sph_nbr* nb) {
     if (!nb) return SPH_OK;
-    (void)hipFree(nb->cell_start);
-    (void)hipFree(nb->scell);
-    (void)hipFree(nb->perm);
-    (void)hipFree(nb->iperm);
-    (void)hipFree(nb->pos);
+    (void)hipFree(nb->blob);
     delete nb;
     return SPH_OK;
 }

@@ -186,7 +186,7 @@ enum Slot : int {
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,
-    kWarmPart2, kWarmU, kList, kWList, kNumSlots
+    kWarmPart2, kWarmU, kList, kWList, kNbrCell, kNbrCount, kNbrFill, kNumSlots
 };
 
 }  // namespace sph
@@ -225,6 +225,7 @@ struct sph_nbr {
     int32_t* perm = nullptr;    // sorted -> original
     int32_t* iperm = nullptr;   // original -> sorted
     sph::Pos4* pos = nullptr;
+    void* blob = nullptr;       // the one device allocation holding the arrays above
     int64_t nnz = -1;           // pair count, computed on demand
 
     sph::NbrView view() const {
