@@ -262,7 +262,8 @@ sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom
  * 3 n x SPH_MLP_SAMPLE) receives sample 3 k + c for particle k (original
  * order) and component c; wall particles get all-zero samples.  u[c],
  * rhs[c], target[c]: device, n doubles each (target may be null: t = 0).
- * *U (host) receives the normalisation.  A u is evaluated in FP64. */
+ * *U (host) receives the normalisation.  A u is evaluated in FP64.
+ * samples must be 16-byte aligned (else SPH_E_ARG). */
 sph_status sph_mlp_samples(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
                            const sph_visc_params *params, const double *const u[3],
                            const double *const rhs[3], const double *const target[3],
@@ -277,7 +278,8 @@ sph_status sph_mlp_warmstart(sph_ctx *ctx, const sph_nbr *nb, const sph_particle
                              const sph_visc_params *params, int32_t prec, const void *const u[3],
                              const void *const rhs[3], const float *mlp_params, void *const x0[3],
                              double *U);
-/* out (device, n x 4) = (o0, o1, o2, pred) of samples (device, n x SPH_MLP_SAMPLE). */
+/* out (device, n x 4) = (o0, o1, o2, pred) of samples (device, n x SPH_MLP_SAMPLE).
+ * samples and out must be 16-byte aligned (else SPH_E_ARG). */
 sph_status sph_mlp_forward(sph_ctx *ctx, const float *samples, int64_t n, const float *params,
                            float *out);
 /* Gradient (device, SPH_MLP_NPARAM) of the mean squared error of the batch

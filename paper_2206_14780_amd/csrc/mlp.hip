@@ -513,6 +513,8 @@ extern "C" sph_status sph_mlp_forward(sph_ctx* ctx, const float* samples, int64_
                                       float* out) {
     if (!ctx) return SPH_E_ARG;
     if (!samples || !params || !out || n < 0) return ctx->fail(SPH_E_ARG, "mlp_forward: bad argument");
+    if (reinterpret_cast<uintptr_t>(samples) % 16 || reinterpret_cast<uintptr_t>(out) % 16)
+        return ctx->fail(SPH_E_ARG, "mlp_forward: samples and out must be 16-byte aligned");
     return sph::mlp::forward(ctx, samples, n, params, out);
 }
 

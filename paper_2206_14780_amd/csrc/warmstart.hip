@@ -71,16 +71,11 @@ __device__ inline void warm_write(int64_t r, const Rhs<C>& rhs, const V3<C>& u, 
     const float f3 = (float)log10(dt * nu / (h * h));
     const double uu[3] = {(double)u.x, (double)u.y, (double)u.z};
     for (int c = 0; c < 3; ++c) {
-        float* o = out + c * kSample;
+        float4* o = reinterpret_cast<float4*>(out + c * kSample);  // rows of 8 floats, 32-byte aligned
         const double uc = uu[c] / U, ic = d[c] / U;
-        o[0] = (float)uc;
-        o[1] = (float)ic;
-        o[2] = f2;
-        o[3] = f3;
-        o[4] = (float)(rhs.at(r, c) / U);
-        o[5] = (float)uc;
-        o[6] = (float)ic;
-        o[7] = tgt ? (float)(tgt[c][rhs.perm[r]] / U) : 0.f;
+        o[0] = float4{(float)uc, (float)ic, f2, f3};
+        o[1] = float4{(float)(rhs.at(r, c) / U), (float)uc, (float)ic,
+                      tgt ? (float)(tgt[c][rhs.perm[r]] / U) : 0.f};
     }
 }
 
@@ -112,7 +107,8 @@ __device__ inline float* sample_row(const FeatArgs<T, C>& a, int64_t r) {
 }
 
 __device__ inline void zero_row(float* o) {
-    for (int k = 0; k < 3 * kSample; ++k) o[k] = 0.f;
+    float4* q = reinterpret_cast<float4*>(o);
+    for (int k = 0; k < 3 * kSample / 4; ++k) q[k] = float4{0.f, 0.f, 0.f, 0.f};
 }
 
 // Cached matrix: d = -sum_k c_k (u_k - u_r) with c = A_rk / D (Jacobi
@@ -470,6 +466,8 @@ extern "C" sph_status sph_mlp_samples(sph_ctx* ctx, const sph_nbr* nb, const sph
                                       double* U) {
     if (!ctx) return SPH_E_ARG;
     if (!samples) return ctx->fail(SPH_E_ARG, "mlp_samples: null samples");
+    if (reinterpret_cast<uintptr_t>(samples) % 16)
+        return ctx->fail(SPH_E_ARG, "mlp_samples: samples not 16-byte aligned");
     SPH_TRY(check_common(ctx, nb, p, params, SPH_F64, (const void* const*)u, (const void* const*)rhs,
                          "mlp_samples"));
     if (target)

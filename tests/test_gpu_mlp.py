@@ -81,6 +81,20 @@ def test_forward_matches_oracle(ctx, m):
     assert rel_l2(g[:, 3], pred) < FWD_REL
 
 
+def test_forward_rejects_misaligned_arrays(ctx):
+    # the inference kernel moves samples and outputs as 16-byte vectors
+    import torch
+    p = _cuda(_params())
+    buf = torch.zeros(17 * 8 + 4, dtype=torch.float32, device="cuda")
+    out = torch.zeros(17 * 4 + 4, dtype=torch.float32, device="cuda")
+    with pytest.raises(S.SphError):
+        ctx.sph_mlp_forward(buf[1:], 16, p, out)
+    with pytest.raises(S.SphError):
+        ctx.sph_mlp_forward(buf, 16, p, out[1:])
+    ctx.sph_mlp_forward(buf[4:], 16, p, out[4:])  # 16-byte offsets are fine
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("batch", [1, 37, 4101, 65536])
 def test_gradient_matches_oracle(ctx, batch):
     import torch
