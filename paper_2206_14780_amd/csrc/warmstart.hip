@@ -32,16 +32,17 @@ struct Rhs {
     __device__ double at(int64_t r, int c) const { return (double)b[c][perm[r]]; }
 };
 
-// Partial sums of b.b over fluid rows and of the fluid row count.
+// Partial sums of b.b over fluid rows and of the fluid row count, in the
+// caller's order (b read contiguously; the type through iperm).
 template <typename C>
-__global__ __launch_bounds__(kBlock) void k_warm_stats(int64_t n, Rhs<C> rhs, const uint8_t* __restrict__ type,
-                                                       double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_warm_stats(int64_t n, Rhs<C> rhs, const int32_t* __restrict__ iperm,
+                                                       const uint8_t* __restrict__ type, double* __restrict__ part) {
     __shared__ double lds[2 * kMaxWaves];
     double acc[2] = {0.0, 0.0};
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        if (type[r] != SPH_FLUID) continue;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (type[iperm[i]] != SPH_FLUID) continue;
         for (int c = 0; c < 3; ++c) {
-            const double v = rhs.at(r, c);
+            const double v = (double)rhs.b[c][i];
             acc[0] += v * v;
         }
         acc[1] += 1.0;
@@ -345,7 +346,8 @@ sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[
     SPH_TRY(ctx->ensure_t(kWarmPart, 2 * kStatBlocks, &part));
     const Rhs<C> rb = make_rhs<C>(w.nb, rhs);
     const int sb = (int)std::min<int64_t>(kStatBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
-    hipLaunchKernelGGL(k_warm_stats<C>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.pv.type, part);
+    hipLaunchKernelGGL(k_warm_stats<C>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.nb->iperm, w.pv.type,
+                       part);
     hipLaunchKernelGGL(k_warm_scale, dim3(1), dim3(kBlock), 0, ctx->stream, (const double*)part, sb, info);
     SPH_LAUNCHED("k_warm_stats/k_warm_scale");
     FeatArgs<T, C> a;
