@@ -162,19 +162,19 @@ struct RowWriter {
         if (j > 0) {
             const int64_t step = (int64_t)col - prev;
             if (needs_escape(step)) {
-                sell_escape(coef, dcol, lo, slot_of(base, j), (int32_t)step);
+                sell_escape(coef, dcol, lo, slot_of<T>(base, j), (int32_t)step);
                 ++j;
                 prev = col;
             }
         } else {
             prev = col;
         }
-        sell_put(coef, dcol, lo, slot_of(base, j), col - prev, c);
+        sell_put(coef, dcol, lo, slot_of<T>(base, j), col - prev, c);
         ++j;
         prev = col;
     }
     __device__ void pad(int32_t width) {
-        for (; j < width; ++j) sell_put(coef, dcol, lo, slot_of(base, j), 0, 0.0);
+        for (; j < width; ++j) sell_put(coef, dcol, lo, slot_of<T>(base, j), 0, 0.0);
     }
 };
 
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_row_count(NbrView nv, PartView pv, O
 }
 
 // Slice size = 64 x (most slots of a row of the slice); nnz += entries.
-__global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslices,
+__global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslices, int32_t pack,
                                                        const int32_t* __restrict__ cnt,
                                                        const int32_t* __restrict__ creal,
                                                        int64_t* __restrict__ size,
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslice
                 tot += creal[r];
             }
         }
-        size[s] = (int64_t)((w + kPack - 1) / kPack * kPack) * kWave;
+        size[s] = (int64_t)((w + pack - 1) / pack * pack) * kWave;
     }
     // one atomic of each kind per wave
     for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
     const int64_t s = r / kWave;
     const int lane = (int)(r % kWave);
     const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
-    RowWriter<T> wr{coef, dcol, lo, lane_base(sl_ptr[s], lane)};
+    RowWriter<T> wr{coef, dcol, lo, lane_base<T>(sl_ptr[s], lane)};
     if (r < nv.n) {
         const int32_t row = (int32_t)r;
         int32_t first = row;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
         return w / sum;
     };
     const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
-    RowWriter<T> wr{coef, dcol, lo, lane_base(sl_ptr[s], r % kWave)};
+    RowWriter<T> wr{coef, dcol, lo, lane_base<T>(sl_ptr[s], r % kWave)};
     int32_t first = row;
     if (listed) {
         for (int32_t k = 0; k < c; ++k) {
@@ -512,7 +512,7 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
                            list);
     }
     hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
-                       n, nslices, cnt, creal, size, nnz_dev);
+                       n, nslices, (int32_t)pack_of<T>(), cnt, creal, size, nnz_dev);
     SPH_LAUNCHED("k_row_count/k_slice_size");
     SPH_TRY(scan_i64(ctx, size, ptr, nslices));
     int64_t nnzp = 0;

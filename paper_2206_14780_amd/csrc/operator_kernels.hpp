@@ -59,47 +59,58 @@ constexpr int group_of() { return sizeof(T) == 4 && !RES ? 16 : 8; }
 // adjacent slots come in one vector load each for the coefficients, the
 // column steps and (residual) the low parts.  Widths and groups are
 // multiples of kPack, so a pack is either wholly inside the row or beyond it.
-template <typename T>
+template <typename T, int P>
 struct Pack {
-    typedef T v __attribute__((ext_vector_type(kPack)));
+    typedef T v __attribute__((ext_vector_type(P)));
 };
-typedef uint16_t u16pack __attribute__((ext_vector_type(kPack)));
+template <typename T>
+struct Pack<T, 1> {
+    typedef T v;
+};
+
+template <typename T, int P>
+__device__ inline T pack_elem(const typename Pack<T, P>::v& v, int e) {
+    if constexpr (P == 1) return v;
+    else return v[e];
+}
 
 template <typename T, bool RES>
 __device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width, int32_t k0,
                                   T (&w)[group_of<T, RES>()], uint16_t (&d)[group_of<T, RES>()],
                                   double (&l)[group_of<T, RES>()]) {
     constexpr int kGroup = group_of<T, RES>();
-    static_assert(kGroup % kPack == 0, "whole packs per group");
+    constexpr int P = pack_of<T>();
+    static_assert(kGroup % P == 0, "whole packs per group");
 #pragma unroll
-    for (int q = 0; q < kGroup / kPack; ++q) {
-        const int32_t k = k0 + q * kPack;
+    for (int q = 0; q < kGroup / P; ++q) {
+        const int32_t k = k0 + q * P;
         if (k < width) {
-            const int64_t i = slot_of(base, k);
+            const int64_t i = slot_of<T>(base, k);
             // read once per launch: non-temporal, so the stream does not
             // evict the x values that the gathers reuse from L2
-            const typename Pack<T>::v wv =
-                __builtin_nontemporal_load(reinterpret_cast<const typename Pack<T>::v*>(A.coef + i));
-            const u16pack dv = __builtin_nontemporal_load(reinterpret_cast<const u16pack*>(A.dcol + i));
+            const typename Pack<T, P>::v wv =
+                __builtin_nontemporal_load(reinterpret_cast<const typename Pack<T, P>::v*>(A.coef + i));
+            const typename Pack<uint16_t, P>::v dv =
+                __builtin_nontemporal_load(reinterpret_cast<const typename Pack<uint16_t, P>::v*>(A.dcol + i));
 #pragma unroll
-            for (int e = 0; e < kPack; ++e) {
-                w[q * kPack + e] = wv[e];
-                d[q * kPack + e] = dv[e];
+            for (int e = 0; e < P; ++e) {
+                w[q * P + e] = pack_elem<T, P>(wv, e);
+                d[q * P + e] = pack_elem<uint16_t, P>(dv, e);
             }
             if constexpr (RES && sizeof(T) == 4) {
-                const typename Pack<float>::v lv = *reinterpret_cast<const typename Pack<float>::v*>(A.lo + i);
+                const typename Pack<float, P>::v lv = *reinterpret_cast<const typename Pack<float, P>::v*>(A.lo + i);
 #pragma unroll
-                for (int e = 0; e < kPack; ++e) l[q * kPack + e] = (double)lv[e];
+                for (int e = 0; e < P; ++e) l[q * P + e] = (double)pack_elem<float, P>(lv, e);
             } else {
 #pragma unroll
-                for (int e = 0; e < kPack; ++e) l[q * kPack + e] = 0.0;
+                for (int e = 0; e < P; ++e) l[q * P + e] = 0.0;
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < kPack; ++e) {
-                w[q * kPack + e] = T(0);
-                d[q * kPack + e] = 0;
-                l[q * kPack + e] = 0.0;
+            for (int e = 0; e < P; ++e) {
+                w[q * P + e] = T(0);
+                d[q * P + e] = 0;
+                l[q * P + e] = 0.0;
             }
         }
     }
@@ -183,7 +194,7 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __
     for (int64_t s = s0 + wid; s < s1; s += nw) {
         const int64_t row = s * kWave + lane;
         if (row >= n) continue;
-        const int64_t base = lane_base(A.sl_ptr[s], lane);
+        const int64_t base = lane_base<T>(A.sl_ptr[s], lane);
         const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
         const V3<XT> xs = ld3(x, row);
         if constexpr (RES) {

@@ -69,10 +69,10 @@ struct OpParams {
 
 // Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).
 // Entry k of row r = s*64 + l lives at slot
-//   sl_ptr[s] + (k / kPack) * 64 kPack + l kPack + k % kPack,
-// i.e. each lane's kPack consecutive entries are adjacent (one vector load)
-// and the 64 lanes' packs of one slot group are contiguous; slice widths are
-// multiples of kPack.  Columns
+//   sl_ptr[s] + (k / P) * 64 P + l P + k % P,
+// with P = pack_of<T>() (4 for FP32 coefficients, 1 for FP64): each lane's P
+// consecutive entries are adjacent (one vector load) and the 64 lanes' packs
+// of one slot group are contiguous; slice widths are multiples of P.  Columns
 // are delta coded: a row's columns ascend; the row starts at column c0[r]
 // and each slot adds its 16-bit step dcol (the first entry steps by 0).  A
 // step that does not fit takes an escape slot (dcol = kEscape) whose
@@ -86,12 +86,19 @@ struct OpParams {
 // lo = coefficient - (double)coef, so coef + lo carries ~48 bits for the
 // FP64-accurate residual.
 constexpr uint16_t kEscape = 0xFFFF;
-constexpr int kPack = 4;
+// Slots of a lane stored together: four FP32 coefficients make one 16-byte
+// load; FP64 keeps one (four measured slower there: more registers, lower
+// occupancy).
+template <typename T>
+constexpr int pack_of() { return sizeof(T) == 4 ? 4 : 1; }
 
 // First slot of lane l of a slice starting at slot sl, and its k-th slot.
-__host__ __device__ inline int64_t lane_base(int64_t sl, int64_t lane) { return sl + lane * kPack; }
+template <typename T>
+__host__ __device__ inline int64_t lane_base(int64_t sl, int64_t lane) { return sl + lane * pack_of<T>(); }
+template <typename T>
 __host__ __device__ inline int64_t slot_of(int64_t lbase, int32_t k) {
-    return lbase + (int64_t)(k / kPack) * (64 * kPack) + k % kPack;
+    constexpr int P = pack_of<T>();
+    return lbase + (int64_t)(k / P) * (64 * P) + k % P;
 }
 
 template <typename T>

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T, C> a, Sel
         if (!fluid) zero_row(o);
         if (!fluid && !a.rplain) continue;
         const int64_t s = r / kWave;
-        const int64_t base = lane_base(A.sl_ptr[s], r % kWave);
+        const int64_t base = lane_base<T>(A.sl_ptr[s], r % kWave);
         const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
         const V3<C> us = ld3(a.u, r);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_wall_sell(int64_t n, Rhs<C> rhs
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || type[r] == SPH_FLUID) return;
     const int64_t s = r / kWave;
-    const int64_t base = lane_base(A.sl_ptr[s], r % kWave);
+    const int64_t base = lane_base<T>(A.sl_ptr[s], r % kWave);
     const int32_t width = (int32_t)((A.sl_ptr[s + 1] - A.sl_ptr[s]) / kWave);
     const V3<T> zero{T(0), T(0), T(0)};
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
