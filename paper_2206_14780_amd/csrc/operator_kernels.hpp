@@ -143,9 +143,12 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
         for (int u = 0; u < kGroup; ++u) {
             const bool esc = rd[u] == kEscape;
             col += esc ? jump_bits(rw[u]) : (int32_t)rd[u];
-            cc[u] = col;
             cw[u] = esc ? T(0) : rw[u];
             cl[u] = esc ? 0.0 : rl[u];
+            // escape and padding slots (zero weight) gather the lane's own
+            // row: the 64 lanes' own rows share a few cache lines, where
+            // their last columns would scatter over many
+            cc[u] = (cw[u] == T(0) && cl[u] == 0.0) ? row : col;
         }
         V3<XT> xv[kGroup];
 #pragma unroll
