@@ -55,6 +55,10 @@ def lib():
         L.orc_bicgstab.argtypes = [C.POINTER(OrcOp), C.c_int32, C.POINTER(dp), C.POINTER(dp),
                                    C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_double,
                                    C.c_int32, C.c_int32, C.POINTER(OrcReport), dp, C.c_int32]
+        L.orc_cg.restype = C.c_int32
+        L.orc_cg.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.POINTER(dp), C.c_double, C.c_int32,
+                             C.c_double, C.c_int32, C.c_int32, C.c_int32, C.POINTER(OrcReport), dp,
+                             C.c_int32]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -244,6 +248,36 @@ def solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, variant=ROBUST, fl
     lib().orc_bicgstab(C.byref(op.s), int(variant), ba, xa, float(tol), int(max_iter),
                        float(floor), int(true_res_period), float(restart_drop), int(fi), int(fc),
                        C.byref(rep), _dp(hist), cap)
+    report = dict(iters=rep.iters, status=rep.status, state=list(rep.state),
+                  stall_count=list(rep.stall_count), rr=list(rep.rr), bb=list(rep.bb),
+                  tau2=list(rep.tau2), true_rr=list(rep.true_rr),
+                  n_true_checks=rep.n_true_checks, n_replaced=rep.n_replaced,
+                  history_len=rep.history_len)
+    return np.stack(xs, axis=1), report, hist[:rep.history_len].copy()
+
+
+def cg_solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, floor=DBL_MIN, true_res_period=50,
+             force_stall=None, history_cap=None):
+    """Rotated CG solve of A V = B (three columns) with the oracle, for the
+    symmetric case (dynamic walls, uniform mass); the wall rows of the start
+    are set to their exact value.  Raises ValueError for dummy walls.
+
+    Returns (X (n,3), report dict, history (len,3) of r.r per iteration)."""
+    B = np.asarray(B, dtype=np.float64)
+    n = op.n
+    bs = [np.ascontiguousarray(B[:, c]) for c in range(3)]
+    X0 = np.zeros((n, 3)) if X0 is None else np.asarray(X0, dtype=np.float64)
+    xs = [np.ascontiguousarray(X0[:, c]).copy() for c in range(3)]
+    cap = int(history_cap or (max_iter + 2))
+    hist = np.zeros((cap, 3))
+    rep = OrcReport()
+    ba = (C.POINTER(C.c_double) * 3)(*[_dp(a) for a in bs])
+    xa = (C.POINTER(C.c_double) * 3)(*[_dp(a) for a in xs])
+    fi, fc = force_stall if force_stall is not None else (-1, -1)
+    st = lib().orc_cg(C.byref(op.s), ba, xa, float(tol), int(max_iter), float(floor), int(true_res_period),
+                      int(fi), int(fc), C.byref(rep), _dp(hist), cap)
+    if st == -1:
+        raise ValueError("CG needs a symmetric system: dynamic walls")
     report = dict(iters=rep.iters, status=rep.status, state=list(rep.state),
                   stall_count=list(rep.stall_count), rr=list(rep.rr), bb=list(rep.bb),
                   tau2=list(rep.tau2), true_rr=list(rep.true_rr),

@@ -21,6 +21,10 @@
  *     sharing one matrix, with the three-state stopping rule
  *                                                 Section "Restructuring the stabilized
  *                                                 biconjugate gradient method"
+ *   - the rotated Conjugate Gradient for the symmetric case (dynamic walls,
+ *     uniform mass)                               Section "Restructuring the Conjugate
+ *                                                 Gradient", Section "Linear system
+ *                                                 properties and resolution"
  *
  * Readings of passages that are ambiguous or inconsistent in the paper:
  *   - Sign of K (eq. kab): the Wendland F is <= 0, so the printed K would be
@@ -46,6 +50,22 @@
  *     restarts the same way.
  *   - textbook variant: when the half-step residual s already meets the
  *     threshold the component takes omega = 0 (x = x + alpha p, r = s).
+ *   - CG with the Jacobi scaling: the paper divides the system by its
+ *     diagonal for both solvers.  D^-1 A is not symmetric, but it is
+ *     self-adjoint in the inner product <u, v>_D = sum_i D_i u_i v_i when A
+ *     is symmetric, so the CG takes its inner products in that product
+ *     (Jacobi-preconditioned CG written for the scaled system); without
+ *     scaling D = 1 and it is the printed rotated CG.  The stopping rule
+ *     uses the Euclidean r.r of the scaled residual, as the BiCGSTAB does.
+ *   - CG and the wall rows: with dynamic walls A is symmetric only on the
+ *     fluid rows (fluid rows see wall columns, wall rows are identity), so
+ *     the start takes the exact value b on every wall row; the wall entries
+ *     of r and p then stay zero and the iteration runs on the symmetric
+ *     fluid block, the paper's reduced system.  Dummy walls break the
+ *     symmetry for good: the CG refuses them.
+ *   - CG stall: alpha = 0 in finite precision (or a zero or non-finite
+ *     p.Ap) while r.r is above the threshold marks the component stalled;
+ *     the iteration completes (a no-op update) and beta is taken as 0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -759,6 +779,161 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
     }
     /* final true residual for the report */
     orc_residual(op, bh, x, tmp, s);
+    int any_prog = 0, any_stall = 0;
+    for (int c = 0; c < 3; ++c) {
+        rep->true_rr[c] = orc_dot(n, tmp[c], tmp[c]);
+        rep->rr[c] = rr[c];
+        rep->tau2[c] = tau2[c];
+        rep->state[c] = state[c];
+        any_prog |= state[c] == ORC_PROGRESSING;
+        any_stall |= state[c] == ORC_STALLED;
+    }
+    rep->iters = it;
+    rep->history_len = hl < history_cap ? hl : history_cap;
+    rep->status = any_prog ? ORC_NOT_CONVERGED : (any_stall ? ORC_STATUS_STALLED : ORC_OK);
+    free(buf);
+    return rep->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rotated CG for d = 3 symmetric systems sharing one matrix (Section       */
+/* "Restructuring the Conjugate Gradient"): p update first, beta last.      */
+/* ------------------------------------------------------------------------ */
+
+/* <a, b>_D = sum_i D_i a_i b_i (D = NULL: the Euclidean product). */
+static double orc_dot_w(int64_t n, const double *D, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (D ? D[i] : 1.0) * a[i] * b[i];
+    return s;
+}
+
+/*
+ * Arguments and report as orc_bicgstab (restart_drop does not apply: the CG
+ * has no shadow vector).  Returns ORC_E_ARG for dummy walls.
+ *
+ * Per component c, with Ah = D^-1 A, bh = D^-1 b under op->jacobi (D = 1
+ * otherwise) and <,> the D-weighted product:
+ *   x_w = bh_w on wall rows;  r_0 = bh - Ah x_0;  rho_0 = <r_0, r_0>;  beta_0 = 0
+ *   iteration i >= 0:
+ *     p_i     = r_i + beta_i p_{i-1}          (p_{i-1} unread when beta_i = 0)
+ *     alpha_i = rho_i / <p_i, Ah p_i>
+ *     r_{i+1} = r_i - alpha_i Ah p_i,  x_{i+1} = x_i + alpha_i p_i
+ *     beta_{i+1} = rho_{i+1} / rho_i,  rho_{i+1} = <r_{i+1}, r_{i+1}>
+ *   converged when r.r < tau^2 (Euclidean, scaled residual).
+ */
+int orc_cg(const orc_op *op, const double *const *b, double *const *x, double tol, int32_t max_iter,
+           double floor_, int32_t true_res_period, int32_t force_stall_iter, int32_t force_stall_comp,
+           orc_report *rep, double *history, int32_t history_cap) {
+    int64_t n = op->n;
+    memset(rep, 0, sizeof(*rep));
+    if (op->wall == ORC_WALL_DUMMY) {
+        rep->status = ORC_E_ARG;
+        return ORC_E_ARG;
+    }
+    double *buf = (double *)calloc((size_t)(n > 0 ? n : 1) * (3 * 5 + 1), sizeof(double));
+    double *bh[3], *r[3], *p[3], *Ap[3], *tmp[3];
+    for (int c = 0; c < 3; ++c) {
+        bh[c] = buf + (0 * 3 + c) * n;
+        r[c] = buf + (1 * 3 + c) * n;
+        p[c] = buf + (2 * 3 + c) * n;
+        Ap[c] = buf + (3 * 3 + c) * n;
+        tmp[c] = buf + (4 * 3 + c) * n;
+    }
+    double *D = NULL;
+    if (op->jacobi) {
+        D = buf + 15 * n;
+        orc_diag(op, D);
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < n; ++i) bh[c][i] = D ? b[c][i] / D[i] : b[c][i];
+    for (int c = 0; c < 3; ++c) {
+        rep->bb[c] = orc_dot(n, bh[c], bh[c]);
+        if (!orc_finite(rep->bb[c])) {
+            free(buf);
+            rep->status = ORC_E_NONFINITE;
+            return ORC_E_NONFINITE;
+        }
+    }
+    /* wall rows are identity rows: start them at their solution */
+    for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < n; ++i)
+            if (op->type[i] != ORC_FLUID) x[c][i] = bh[c][i];
+    orc_residual(op, bh, x, r, tmp);
+    double rho[3], beta[3], tau2[3], rr[3];
+    int state[3], restarts[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        tau2[c] = tol * tol * rep->bb[c];
+        if (tau2[c] < floor_) tau2[c] = floor_;
+        rr[c] = orc_dot(n, r[c], r[c]);
+        rho[c] = orc_dot_w(n, D, r[c], r[c]);
+        beta[c] = 0.0;
+        state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+        if (history && history_cap > 0) history[c] = rr[c];
+    }
+    int hl = 1;
+    int it = 0;
+    for (;;) {
+        int any_prog = 0;
+        for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
+        int periodic_check = (it > 0 && true_res_period > 0 && it % true_res_period == 0);
+        if (!any_prog || periodic_check) {
+            /* true residual; a converged component that fails it restarts
+             * from r_true with beta = 0 (at most ORC_MAX_RESTARTS times) */
+            rep->n_true_checks++;
+            orc_residual(op, bh, x, tmp, Ap);
+            for (int c = 0; c < 3; ++c) {
+                double trr = orc_dot(n, tmp[c], tmp[c]);
+                if (state[c] == ORC_CONVERGED && !(trr < tau2[c])) {
+                    if (restarts[c] >= ORC_MAX_RESTARTS) {
+                        state[c] = ORC_STALLED;
+                    } else {
+                        restarts[c]++;
+                        memcpy(r[c], tmp[c], sizeof(double) * (size_t)n);
+                        rr[c] = trr;
+                        rho[c] = orc_dot_w(n, D, r[c], r[c]);
+                        beta[c] = 0.0;
+                        state[c] = trr < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+                        rep->n_replaced++;
+                    }
+                }
+            }
+            any_prog = 0;
+            for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
+        }
+        if (!any_prog || it >= max_iter) break;
+        ++it;
+        int stall[3] = {0, 0, 0};
+        /* p_i = r_i + beta_i p_{i-1} */
+        for (int c = 0; c < 3; ++c)
+            for (int64_t i = 0; i < n; ++i) p[c][i] = beta[c] != 0.0 ? r[c][i] + beta[c] * p[c][i] : r[c][i];
+        orc_apply(op, (const double *const *)p, Ap);
+        for (int c = 0; c < 3; ++c) {
+            double pap = orc_dot_w(n, D, p[c], Ap[c]);
+            if (it == force_stall_iter && c == force_stall_comp) pap = 0.0;
+            double a = 0.0;
+            if (pap != 0.0 && orc_finite(pap)) a = rho[c] / pap;
+            if (!orc_finite(a) || a == 0.0) {
+                a = 0.0;
+                stall[c] = 1;
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                x[c][i] = x[c][i] + a * p[c][i];
+                r[c][i] = r[c][i] - a * Ap[c][i];
+            }
+            double rho_new = orc_dot_w(n, D, r[c], r[c]);
+            double bt = 0.0;
+            if (!stall[c] && rho[c] != 0.0) bt = rho_new / rho[c];
+            if (!orc_finite(bt)) bt = 0.0;
+            beta[c] = bt;
+            rho[c] = rho_new;
+            rr[c] = orc_dot(n, r[c], r[c]);
+            if (stall[c]) rep->stall_count[c]++;
+            state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : (stall[c] ? ORC_STALLED : ORC_PROGRESSING);
+            if (history && hl < history_cap) history[3 * hl + c] = rr[c];
+        }
+        ++hl;
+    }
+    orc_residual(op, bh, x, tmp, Ap);
     int any_prog = 0, any_stall = 0;
     for (int c = 0; c < 3; ++c) {
         rep->true_rr[c] = orc_dot(n, tmp[c], tmp[c]);
