@@ -17,6 +17,8 @@ workload, and the plain-versus-learned comparison: on held-out 160^3 boxes
 (4,491,628 particles) of the learned start's workload family, the time to a
 1e-6 relative residual of the plain previous-step start with the FP64
 operator against the learned start with the FP32 operator (FP64 solution).
+Also reported: whole steps of the robust BiCGSTAB and of the rotated CG on
+the same tank with dynamic walls (the symmetric case the CG is for).
 """
 import argparse
 import json
@@ -67,6 +69,9 @@ def parse():
                     help="fluid particles per side of the plain-vs-learned boxes (0 = skip)")
     ap.add_argument("--learned-seeds", type=int, default=3, help="held-out boxes compared")
     ap.add_argument("--learned-reps", type=int, default=2, help="timed solves per box and start")
+    ap.add_argument("--cg-n", type=int, default=100,
+                    help="tank side of the CG-versus-BiCGSTAB comparison on dynamic walls (0 = skip)")
+    ap.add_argument("--cg-steps", type=int, default=3, help="timed steps per solver in that comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device once "
                          "(a kernel of known traffic to scale hardware byte counters)")
@@ -140,6 +145,66 @@ def plain_vs_learned(ctx, n, seeds, reps):
             "speedup_median": round(float(np.median([r["speedup"] for r in rows])), 3),
             "speedup_min": round(float(np.min([r["speedup"] for r in rows])), 3),
             "boxes": rows}
+
+
+def cg_vs_bicgstab(ctx, n, steps, prec_name):
+    """Whole steps (neighbour build + operator build + solve) of the robust
+    BiCGSTAB and of the rotated CG on the symmetric variant of the tank
+    (dynamic walls, uniform mass), FP32 operator and vectors, to 1e-6."""
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import workloads as W
+
+    prec = S.SPH_F32 if prec_name == "f32" else S.SPH_F64
+    esz = 4 if prec == S.SPH_F32 else 8
+    w = W.open_box(n=n, wall=W.WALL_DYNAMIC)
+    parts = S.device_particles(w)
+    dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
+    rhs = S.device_vec3(w.rhs, prec)
+    x0 = S.device_vec3(w.x0, prec)
+    x = [t.clone() for t in x0]
+    params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
+    out = {"workload": f"open-top tank {n}^3 jittered fluid + 3 wall layers (dynamic), uniform mass, nu=10, "
+                       f"dt*nu/dp^2=50, {prec_name} vectors/operator + f64 scalars, cached operator, "
+                       f"previous-step start, tol 1e-6; whole step (neighbours + matrix + solve)",
+           "n_particles": w.n}
+    for name, variant, applies in (("bicgstab", S.SPH_ROBUST, 2), ("cg", S.SPH_CG, 1)):
+        opts = S.make_opts(tol=w.tol, x0_given=True, profile=PROFILE_EVERY, variant=variant)
+
+        def step():
+            for a, b in zip(x, x0):
+                a.copy_(b)
+            nb = ctx.sph_build_neighbors(parts, dom)
+            rep = ctx.sph_visc_solve(nb, None, parts, params, prec, rhs, x, opts)
+            nb.free()
+            assert rep["status"] == S.SPH_OK, (name, rep)
+            return rep
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = reps[-1]
+        a_ms = sum(q["apply_ms"] for q in reps) / max(sum(q["apply_launches"] for q in reps), 1)
+        nslices = (w.n + 63) // 64
+        # as the headline roofline, plus the CG's FP64 weight per row
+        alg = r["mat_nnz"] * (4 + esz) + w.n * (7 * esz) + nslices * 8 + (w.n * 8 if variant == S.SPH_CG else 0)
+        out[name] = {"ms_per_step": round(ms, 3), "iterations": r["iters"],
+                     "applies_per_solve": r["iters"] * applies,
+                     "time_to_tol_ms": round(float(np.median([q["setup_ms"] + q["iterate_ms"] for q in reps])), 3),
+                     "true_rel_res": round(max(float(np.sqrt(t / b)) for t, b in zip(r["true_rr"], r["bb"]) if b > 0), 9),
+                     "timed_kernel": "k_apply_sell<" + ("float" if esz == 4 else "double") + (
+                         ", kDotCG>" if variant == S.SPH_CG else ", kDotA2>"),
+                     "avg_launch_ms": round(a_ms, 4),
+                     "hbm_frac": round(alg / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if a_ms > 0 else None}
+        print(f"[bench] {name} on dynamic walls: {json.dumps(out[name])}", flush=True)
+    out["cg_speedup"] = round(out["bicgstab"]["ms_per_step"] / out["cg"]["ms_per_step"], 3)
+    out["paper_context"] = "the paper reports the CG about 10% faster than the BiCGSTAB with dynamic walls"
+    return out
 
 
 def main():
@@ -225,6 +290,11 @@ def main():
         print("[bench] plain vs learned", flush=True)
         pvl = plain_vs_learned(ctx, args.learned_n, args.learned_seeds, args.learned_reps)
 
+    cg = None
+    if args.cg_n > 0:
+        print("[bench] CG vs BiCGSTAB (dynamic walls)", flush=True)
+        cg = cg_vs_bicgstab(ctx, args.cg_n, args.cg_steps, args.prec)
+
     cpu = None
     if args.cpu_sample_iters > 0:
         print("[bench] cpu baseline (oracle)", flush=True)
@@ -255,6 +325,7 @@ def main():
         "launches_per_solve": reps[-1]["launches"],
         "roofline": roofline,
         "plain_vs_learned": pvl,
+        "cg_vs_bicgstab": cg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -10,7 +10,9 @@
  *
  * three systems (one per velocity component) sharing one matrix, solved by
  * the paper's restructured ("robust") BiCGSTAB (Section "Restructuring the
- * stabilized biconjugate gradient method") or by the textbook BiCGSTAB.
+ * stabilized biconjugate gradient method"), by the textbook BiCGSTAB, or,
+ * when the system is symmetric, by the paper's rotated Conjugate Gradient
+ * (Section "Restructuring the Conjugate Gradient").
  *
  * Conventions for every call:
  *   - Pointers inside sph_particles and the x/y/rhs arrays are DEVICE pointers
@@ -66,7 +68,7 @@ enum { SPH_F64 = 0, SPH_F32 = 1, SPH_MIXED = 2 };
 enum { SPH_FLUID = 0, SPH_WALL = 1 };              /* particle type */
 enum { SPH_WALL_DYNAMIC = 0, SPH_WALL_DUMMY = 1 }; /* boundary model (Section "Boundary conditions") */
 enum { SPH_AVG_ARITH = 0, SPH_AVG_HARMONIC = 1 };  /* pairwise viscosity mean (Section "Discretized equations") */
-enum { SPH_ROBUST = 0, SPH_STANDARD = 1 };         /* BiCGSTAB variant */
+enum { SPH_ROBUST = 0, SPH_STANDARD = 1, SPH_CG = 2 }; /* solver: robust / textbook BiCGSTAB, rotated CG */
 enum { SPH_OP_CACHED = 0, SPH_OP_ONTHEFLY = 1 };   /* operator evaluation (see sph_visc_params) */
 enum { SPH_CONVERGED = 0, SPH_STATE_STALLED = 1, SPH_PROGRESSING = 2 }; /* per-component state */
 
@@ -105,6 +107,17 @@ typedef struct {
 } sph_visc_params;
 
 /* Solver options.
+ *   variant: SPH_ROBUST, SPH_STANDARD or SPH_CG.  The CG needs a symmetric
+ *          system (Section "Linear system properties and resolution"):
+ *          dynamic walls (dummy walls: SPH_E_ARG) and uniform particle mass
+ *          (not checked; with unequal masses it may stall or not converge).
+ *          It starts the wall rows at their exact value (b), so that the
+ *          iteration runs on the symmetric fluid block, and with jacobi it
+ *          takes its inner products weighted by D = diag(A), the form in
+ *          which D^-1 A is self-adjoint (Jacobi-preconditioned CG).  One
+ *          operator pass per iteration (the BiCGSTAB takes two).
+ *          restart_drop does not apply to it; force_stall_iter treats
+ *          p . A p as zero.
  *   tol:   relative tolerance eps; component c converges when r.r < tau2_c,
  *          tau2_c = max(eps^2 b.b, floor) on the (scaled) system
  *          (Section "Restructuring the Conjugate Gradient", stopping criterion).
@@ -119,7 +132,7 @@ typedef struct {
  *   force_stall_iter / force_stall_comp: test hook; at that iteration that
  *          component's delta is treated as zero.  -1 = off.
  *   profile: k > 0 = bracket the second operator launch (A r_star and its
- *          dot products) of every k-th iteration with HIP events on the
+ *          dot products; the CG's only one) of every k-th iteration with HIP events on the
  *          context stream and report the total time of the executed ones
  *          (apply_ms, apply_launches); 0 = off.  Each event pair leaves a
  *          gap of a few microseconds in the stream, so k > 1 keeps the
@@ -144,7 +157,7 @@ typedef struct {
 typedef struct {
     double tol;
     int32_t max_iter;
-    int32_t variant; /* SPH_ROBUST / SPH_STANDARD */
+    int32_t variant; /* SPH_ROBUST / SPH_STANDARD / SPH_CG */
     double floor;
     int32_t true_res_period;
     int32_t x0_given;

@@ -15,17 +15,25 @@ namespace sph {
 //   kDotA2Std  9 partials: as kDotA2 plus x . x (textbook half-step check)
 //   kDotResid  3 partials: y . y with y = b - A x evaluated in FP64 with the
 //              FP64-accurate coefficients (true residual)
-enum DotMode { kDotNone = 0, kDotA1 = 1, kDotA2 = 2, kDotA2Std = 3, kDotResid = 4 };
+//   kDotCG     3 partials: <x, y>_D = sum_i D_i x_i y_i, the CG's p . A p in
+//              the Jacobi-weighted inner product (D from the FP64 argument;
+//              null: D = 1)
+enum DotMode { kDotNone = 0, kDotA1 = 1, kDotA2 = 2, kDotA2Std = 3, kDotResid = 4, kDotCG = 5 };
 
 template <int MODE>
 struct DotK {
     static constexpr int K = MODE == kDotA1 ? 3 : MODE == kDotA2 ? 6 : MODE == kDotA2Std ? 9
-                             : MODE == kDotResid ? 3 : 1;
+                             : MODE == kDotResid ? 3 : MODE == kDotCG ? 3 : 1;
 };
 
 template <typename T, int MODE>
-__device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V3<T> yv, V3<T> wv) {
-    if constexpr (MODE == kDotA1) {
+__device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V3<T> yv, V3<T> wv,
+                                       double dw = 1.0) {
+    if constexpr (MODE == kDotCG) {
+        acc[0] += dw * (double)xs.x * (double)yv.x;
+        acc[1] += dw * (double)xs.y * (double)yv.y;
+        acc[2] += dw * (double)xs.z * (double)yv.z;
+    } else if constexpr (MODE == kDotA1) {
         acc[0] += (double)wv.x * (double)yv.x;
         acc[1] += (double)wv.y * (double)yv.y;
         acc[2] += (double)wv.z * (double)yv.z;
@@ -174,7 +182,8 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
 // One wavefront per 64-row slice; each block takes a contiguous range of
 // slices (XCD-aware order) and its waves interleave over it.  With kDotResid
 // the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead, and
-// x may be held in another precision XT.
+// x may be held in another precision XT; with kDotCG, b64 holds the weights
+// D of the inner product.
 template <typename T, int MODE, typename XT = T>
 __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
                                                           const XT* __restrict__ x, T* __restrict__ y,
@@ -224,7 +233,9 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __
             if constexpr (MODE != kDotNone) {
                 V3<T> wv{};
                 if constexpr (MODE == kDotA1) wv = ld3(w, row);
-                accumulate_dots<T, MODE>(acc, xs, yv, wv);
+                double dw = 1.0;
+                if constexpr (MODE == kDotCG) dw = b64 ? b64[row] : 1.0;
+                accumulate_dots<T, MODE>(acc, xs, yv, wv, dw);
             }
         }
     }
@@ -280,7 +291,7 @@ __device__ inline void row_apply_otf(const NbrView& nv, const PartView& pv, cons
 
 // On-the-fly operator over rows in cell order; with kDotResid it writes
 // y = b64 - A x instead (FP64 residual rounded to T) and its squared norm,
-// x then being of precision XT.
+// x then being of precision XT; with kDotCG, b64 holds the weights D.
 template <typename T, int MODE, typename XT = T>
 __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_otf(const int32_t* __restrict__ halt, NbrView nv, PartView pv,
                                                          OpParams op, const XT* __restrict__ x, T* __restrict__ y,
@@ -316,7 +327,9 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_otf(const int32_t* __r
         if constexpr (MODE != kDotNone && MODE != kDotResid) {
             V3<T> wv{};
             if constexpr (MODE == kDotA1) wv = ld3(w, r);
-            accumulate_dots<T, MODE>(acc, ld3(x, r), out, wv);
+            double dw = 1.0;
+            if constexpr (MODE == kDotCG) dw = b64 ? b64[r] : 1.0;
+            accumulate_dots<T, MODE>(acc, ld3(x, r), out, wv, dw);
         }
     }
     if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);

@@ -7,6 +7,12 @@
 //   S   s = r - alpha A p                 (the paper's r_star)
 //   A2  A s, and partials of s . A s, A s . A s (and s . s for the textbook check)
 //   K3  x = x + alpha p + omega s, r = s - omega A s, partials of r0hat . r and r . r
+// The rotated CG for symmetric systems (Section "Restructuring the Conjugate
+// Gradient") takes three: P (p = r + beta p, partials of rho = <r, r>_D),
+// A (A p, partials of <p, A p>_D) and K (alpha = rho / <p, A p>_D,
+// x = x + alpha p, r = r - alpha A p, partials of <r, r>_D and r . r), with
+// <u, v>_D = sum_i D_i u_i v_i under the Jacobi scaling (D^-1 A is
+// self-adjoint in it when A is symmetric; D = 1 without scaling).
 // plus, every `true_res_period` iterations, the FP64-accurate residual
 // b - A x, whose outcome the next P applies (restart of a component that the
 // recursion calls converged but the true residual does not).
@@ -95,6 +101,15 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
                     if (!finite_d(bt)) bt = 0.0;
                 }
                 if (g == 0.0) stall = 1;
+            } else if (sc.variant == SPH_CG) {
+                // beta_{j+1} = rho_{j+1}/rho_j: g = <r, r>_D from the
+                // close-out's partials, rho_j as the close-out stored it;
+                // 0 after a stalled iteration
+                if (!stall) {
+                    const double rp = ctl->gam[prev][c];
+                    if (rp != 0.0) bt = g / rp;
+                    if (!finite_d(bt)) bt = 0.0;
+                }
             } else {
                 // beta_{j+1} = (gamma_{j+1}/gamma_j)(alpha_j/omega_j)
                 const double gp = ctl->gam[prev][c], al = ctl->alpha[prev][c], om = ctl->omega[prev][c];
@@ -160,13 +175,16 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
     o.reason = reason;
 }
 
+// CG: dw (null: 1) weighs the partials of rho = <r, r>_D written to
+// part_rho, taken after any restart copy (the r that p is built from).
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                     const double* __restrict__ part, int32_t nblk,
                                                     const double* __restrict__ part_tr, int64_t n, T* __restrict__ r,
                                                     T* __restrict__ rh0, T* __restrict__ p,
                                                     const T* __restrict__ ap, const T* __restrict__ rt,
-                                                    double* __restrict__ hist, int32_t* __restrict__ stallhist) {
+                                                    double* __restrict__ hist, int32_t* __restrict__ stallhist,
+                                                    const double* __restrict__ dw, double* __restrict__ part_rho) {
     if (ctl->halt) return;
     __shared__ double lds[kKp * kMaxWaves];
     double red[kKp];
@@ -214,12 +232,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
         if (s.reason) ctl->halt = 1;
     }
     if (s.reason) return;
-    // body: p update; a zero coefficient skips its vector
+    // body: p update; a zero coefficient skips its vector (the robust form
+    // also serves the CG, whose alpha' is 0)
+    const bool textbook = sc.variant == SPH_STANDARD;
     const bool use_p = s.bt[0] != 0.0 || s.bt[1] != 0.0 || s.bt[2] != 0.0;
-    const bool use_ap = sc.variant == SPH_ROBUST ? (s.ap[0] != 0.0 || s.ap[1] != 0.0 || s.ap[2] != 0.0) : use_p;
+    const bool use_ap = !textbook ? (s.ap[0] != 0.0 || s.ap[1] != 0.0 || s.ap[2] != 0.0) : use_p;
     const bool any_rs = s.restart[0] | s.restart[1] | s.restart[2];
     double om[3];
-    for (int c = 0; c < 3; ++c) om[c] = sc.variant == SPH_ROBUST ? 0.0 : (it > 1 ? ctl->omega[j & 1][c] : 1.0);
+    for (int c = 0; c < 3; ++c) om[c] = !textbook ? 0.0 : (it > 1 ? ctl->omega[j & 1][c] : 1.0);
+    double acc[3] = {0.0, 0.0, 0.0};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
     const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
@@ -241,7 +262,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
         const T pp[3] = {pv.x, pv.y, pv.z};
         const T aa[3] = {av.x, av.y, av.z};
         for (int c = 0; c < 3; ++c) {
-            if (sc.variant == SPH_ROBUST) {
+            if (!textbook) {
                 if (s.bt[c] != 0.0) o[c] = o[c] + (T)s.bt[c] * pp[c];
                 if (s.ap[c] != 0.0) o[c] = o[c] - (T)s.ap[c] * aa[c];
             } else if (s.bt[c] != 0.0) {
@@ -249,7 +270,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
             }
         }
         st3(p, i, V3<T>{o[0], o[1], o[2]});
+        if (part_rho) {
+            const double d = dw ? dw[i] : 1.0;
+            acc[0] += d * (double)rv.x * (double)rv.x;
+            acc[1] += d * (double)rv.y * (double)rv.y;
+            acc[2] += d * (double)rv.z * (double)rv.z;
+        }
     }
+    if (part_rho) write_partials<3>(acc, lds, part_rho);
 }
 
 // alpha_i = gamma_i/delta_i, then s = r - alpha A p.
@@ -364,6 +392,88 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
         st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
     }
     write_partials<kKp>(acc, lds, part_out);
+}
+
+// CG close-out: alpha = rho / <p, A p>_D (0, and the component stalled,
+// when that is zero or not finite); x = x + alpha p; r = r - alpha A p;
+// partials (kKp per block) of <r, r>_D, r . r and three zeros, the layout
+// the p update reads.  rho_i is stored as gam[it & 1] for the next beta.
+template <typename T, typename X>
+__global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
+                                                        const double* __restrict__ part_rho, int32_t nrho,
+                                                        const double* __restrict__ part_pap, int32_t npap,
+                                                        int64_t n, X* __restrict__ x, const T* __restrict__ p,
+                                                        const T* __restrict__ ap, T* __restrict__ r,
+                                                        const double* __restrict__ dw,
+                                                        double* __restrict__ part_out) {
+    if (ctl->halt) return;
+    __shared__ double lds[kKp * kMaxWaves];
+    double rho[3], pap[3];
+    reduce_partials<3>(part_rho, nrho, rho, lds);
+    reduce_partials<3>(part_pap, npap, pap, lds);
+    const int cur = it & 1;
+    double al[3];
+    int32_t stall[3];
+    for (int c = 0; c < 3; ++c) {
+        double d = pap[c];
+        if (it == sc.force_stall_iter && c == sc.force_stall_comp) d = 0.0;
+        pap[c] = d;
+        double a = 0.0;
+        if (d != 0.0 && finite_d(d)) a = rho[c] / d;
+        stall[c] = 0;
+        if (!finite_d(a) || a == 0.0) {
+            a = 0.0;
+            stall[c] = 1;
+        }
+        al[c] = a;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            ctl->gam[cur][c] = rho[c];
+            ctl->delta[cur][c] = pap[c];
+            ctl->alpha[cur][c] = al[c];
+            ctl->stallB[cur][c] = stall[c];
+        }
+    }
+    double acc[kKp];
+#pragma unroll
+    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    const T A[3] = {(T)al[0], (T)al[1], (T)al[2]};
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
+    const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const V3<X> xv = ld3(x, i);
+        const V3<T> pv = ld3(p, i), av = ld3(ap, i), rv = ld3(r, i);
+        const X xx[3] = {xv.x, xv.y, xv.z};
+        const T pp[3] = {pv.x, pv.y, pv.z}, aa[3] = {av.x, av.y, av.z}, rr[3] = {rv.x, rv.y, rv.z};
+        const double d = dw ? dw[i] : 1.0;
+        X xo[3];
+        T ro[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (sizeof(X) == sizeof(T)) xo[c] = xx[c] + A[c] * pp[c];
+            else xo[c] = (double)xx[c] + al[c] * (double)pp[c];
+            ro[c] = rr[c] - A[c] * aa[c];
+            acc[c] += d * (double)ro[c] * (double)ro[c];
+            acc[3 + c] += (double)ro[c] * (double)ro[c];
+        }
+        st3(x, i, V3<X>{xo[0], xo[1], xo[2]});
+        st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
+    }
+    write_partials<kKp>(acc, lds, part_out);
+}
+
+// CG start: wall rows (identity rows of the dynamic-wall system) take their
+// exact value, so r and p stay zero there and the iteration runs on the
+// symmetric fluid block (Section "Linear system properties and resolution").
+template <typename X>
+__global__ __launch_bounds__(kBlock) void k_cg_walls(int64_t n, const uint8_t* __restrict__ type,
+                                                     const double* __restrict__ b64, X* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || type[i] == SPH_FLUID) return;
+    const V3<double> b = ld3(b64, i);
+    st3(x, i, V3<X>{(X)b.x, (X)b.y, (X)b.z});
 }
 
 // Host-issued residual check, step 2 (one block): decide which converged
@@ -505,6 +615,7 @@ struct Solver {
     int32_t mode;
     Sell<T> sell{};
     const double* diag64 = nullptr;
+    const double* dw = nullptr;  // CG inner-product weights: D under the Jacobi scaling, else null (1)
     Launch L;
     T *b, *r, *rh0, *p, *ap, *s, *as, *tmp;
     X* x;
@@ -540,33 +651,59 @@ struct Solver {
     dim3 bs() const { return dim3(L.block_stream); }
 
     // y = A x fused with the dot products of mode MODE (x of precision XT:
-    // T, or X for the true residual)
+    // T, or X for the true residual); kDotCG weighs its products by dw
     template <int MODE, typename XT = T>
     void apply(const int32_t* halt, const XT* xin, T* yout, const T* w, double* part) {
+        const double* aux = MODE == kDotCG ? dw : b64;
         if (mode == SPH_OP_CACHED)
             hipLaunchKernelGGL((k_apply_sell<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, L.n, sell, xin, yout,
-                               w, (const double*)b64, part);
+                               w, aux, part);
         else
             hipLaunchKernelGGL((k_apply_otf<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, nb->view(), pv, op,
-                               xin, yout, w, (const double*)b64, part);
+                               xin, yout, w, aux, part);
         ++launches;
     }
 
-    sph_status iteration(int32_t it) {
+    // events around the timed operator launch of iteration `it`
+    sph_status time_begin(int32_t it, hipEvent_t* ev1) {
+        *ev1 = nullptr;
+        if (!(profile > 0 && it % profile == 0)) return SPH_OK;
+        const int k = (int)recs.size();
+        hipEvent_t ev0 = nullptr;
+        SPH_TRY(prof_event(2 * k, &ev0));
+        SPH_TRY(prof_event(2 * k + 1, ev1));
+        recs.push_back(Rec{it, round, k});
+        SPH_HIP(hipEventRecord(ev0, ctx->stream));
+        return SPH_OK;
+    }
+
+    // rotated CG: P (p and the partials of rho), A (A p, <p, A p>_D), K
+    sph_status iteration_cg(int32_t it) {
         const int32_t* halt = &ctl->halt;
         hipLaunchKernelGGL(k_pupd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
-                           (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist);
+                           (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist, dw, pa2);
+        hipEvent_t ev1 = nullptr;
+        SPH_TRY(time_begin(it, &ev1));
+        apply<kDotCG>(halt, p, ap, nullptr, pa1);
+        if (ev1) SPH_HIP(hipEventRecord(ev1, ctx->stream));
+        hipLaunchKernelGGL((k_cg_close<T, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, (const double*)pa2,
+                           L.grid_stream, (const double*)pa1, L.grid_apply, L.n, x, p, ap, r, dw, pk3);
+        launches += 2;
+        if (sc.true_res_period > 0 && it % sc.true_res_period == 0) true_residual(halt, ptr);
+        return SPH_OK;
+    }
+
+    sph_status iteration(int32_t it) {
+        if (sc.variant == SPH_CG) return iteration_cg(it);
+        const int32_t* halt = &ctl->halt;
+        hipLaunchKernelGGL(k_pupd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
+                           (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist, (const double*)nullptr,
+                           (double*)nullptr);
         apply<kDotA1>(halt, p, ap, rh0, pa1);
         hipLaunchKernelGGL(k_supd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pa1, L.grid_apply, L.n, r, ap, s);
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        const bool timed = profile > 0 && it % profile == 0;
-        if (timed) {
-            const int k = (int)recs.size();
-            SPH_TRY(prof_event(2 * k, &ev0));
-            SPH_TRY(prof_event(2 * k + 1, &ev1));
-            recs.push_back(Rec{it, round, k});
-            SPH_HIP(hipEventRecord(ev0, ctx->stream));
-        }
+        hipEvent_t ev1 = nullptr;
+        SPH_TRY(time_begin(it, &ev1));
+        const bool timed = ev1 != nullptr;
         if (sc.variant == SPH_STANDARD) {
             apply<kDotA2Std>(halt, s, as, nullptr, pa2);
             if (timed) SPH_HIP(hipEventRecord(ev1, ctx->stream));
@@ -648,7 +785,10 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
 
     S.sc.tol2 = o->tol * o->tol;
     const bool vec32 = sizeof(T) == 4;
-    S.sc.drop = o->restart_drop >= 0.0 ? o->restart_drop : 0.1;
+    const bool cg = o->variant == SPH_CG;
+    // the drop restart renews the BiCGSTAB's shadow vector; the CG has none
+    S.sc.drop = cg ? 0.0 : (o->restart_drop >= 0.0 ? o->restart_drop : 0.1);
+    S.dw = cg && S.op.jacobi ? S.diag64 : nullptr;
     S.sc.tr_blocks = L.grid_apply;
     S.sc.floor_ = o->floor >= 0.0 ? o->floor : (vec32 ? (double)FLT_MIN : DBL_MIN);
     S.sc.max_iter = o->max_iter;
@@ -711,13 +851,21 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
         S.launches += 11;
         SPH_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
     } else if (o->x0_given) {
-        // r0 = b - A x0 with the FP64-accurate operator
         SPH_TRY(gather_vec3<X>(ctx, nb, (const void* const*)xout, S.x));
+    } else {
+        SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
+    }
+    if (cg) {
+        // the CG starts the wall rows at their exact value
+        hipLaunchKernelGGL(k_cg_walls<X>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
+                           S.pv.type, (const double*)S.b64, S.x);
+        ++S.launches;
+    }
+    if (cg || (!o->warm_params && o->x0_given)) {
+        // r0 = b - A x0 with the FP64-accurate operator
         S.true_residual(nullptr, S.pchk);
         r0 = S.tmp;
         ++S.launches;
-    } else {
-        SPH_HIP(hipMemsetAsync(S.x, 0, sizeof(X) * v3, ctx->stream));
     }
     SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
     SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
@@ -870,8 +1018,10 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
         if (!rhs[c] || !x[c]) return ctx->fail(SPH_E_ARG, "visc_solve: null vector");
     if (!(opts->tol >= 0.0) || opts->max_iter < 0 || opts->max_iter > 100000000)
         return ctx->fail(SPH_E_ARG, "visc_solve: tol or max_iter out of range");
-    if (opts->variant != SPH_ROBUST && opts->variant != SPH_STANDARD)
+    if (opts->variant != SPH_ROBUST && opts->variant != SPH_STANDARD && opts->variant != SPH_CG)
         return ctx->fail(SPH_E_ARG, "visc_solve: variant");
+    if (opts->variant == SPH_CG && params && params->wall == SPH_WALL_DUMMY)
+        return ctx->fail(SPH_E_ARG, "visc_solve: the CG needs a symmetric system (dynamic walls)");
     if (opts->true_res_period < 0) return ctx->fail(SPH_E_ARG, "visc_solve: true_res_period < 0");
     sph_nbr* own = nullptr;
     if (!nb) {

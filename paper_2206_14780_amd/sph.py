@@ -22,7 +22,7 @@ SPH_E_ARG, SPH_E_OOM, SPH_E_HIP, SPH_E_OVERFLOW, SPH_E_NONFINITE = -1, -2, -3, -
 SPH_F64, SPH_F32, SPH_MIXED = 0, 1, 2
 SPH_WALL_DYNAMIC, SPH_WALL_DUMMY = 0, 1
 SPH_AVG_ARITH, SPH_AVG_HARMONIC = 0, 1
-SPH_ROBUST, SPH_STANDARD = 0, 1
+SPH_ROBUST, SPH_STANDARD, SPH_CG = 0, 1, 2
 SPH_OP_CACHED, SPH_OP_ONTHEFLY = 0, 1
 SPH_CONVERGED, SPH_STATE_STALLED, SPH_PROGRESSING = 0, 1, 2
 SPH_MLP_NPARAM, SPH_MLP_SAMPLE = 8835, 8

@@ -1,0 +1,150 @@
+"""GPU parity of the rotated CG (Section "Restructuring the Conjugate
+Gradient") against the oracle's CG on symmetric systems (dynamic walls,
+uniform mass): FP64 solutions within 1e-10 and the same iteration count,
+FP32 and mixed within 1e-5, the stall rule, the true-residual checks, the
+start handling and the full-size tank on sampled rows."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_14780_amd import sph as S
+from paper_2206_14780_amd import workloads as W
+
+from gpu_util import GpuCase, oracle_op, rel_l2, small_tank
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return S.Context(0)
+
+
+def _uniform_mass(w):
+    return dataclasses.replace(w, mass=np.full(w.n, 1.0))
+
+
+def _systems():
+    return [
+        W.with_random_order(W.poiseuille(16, wall=W.WALL_DYNAMIC), 1),
+        _uniform_mass(small_tank(seed=22, wall=W.WALL_DYNAMIC)),   # N = 396: ragged last slice
+        _uniform_mass(small_tank(seed=23, n=(7, 5, 4), wall=W.WALL_DYNAMIC, avg=W.AVG_ARITH)),
+        W.open_box(n=11, seed=12, wall=W.WALL_DYNAMIC),
+    ]
+
+
+def _walls_exact(w, X, B):
+    wr = w.ptype != W.FLUID
+    return np.array_equal(X[wr], B[wr])
+
+
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+@pytest.mark.parametrize("jacobi", [True, False])
+@pytest.mark.parametrize("idx", range(4))
+def test_cg_fp64_matches_oracle(ctx, op_mode, jacobi, idx):
+    w = _systems()[idx]
+    print(f"[cg64] {w.name} jacobi={jacobi} mode={op_mode}", flush=True)
+    B = w.rhs.copy()
+    wr = w.ptype != W.FLUID
+    B[wr] = np.random.default_rng(idx).normal(scale=0.1, size=(int(wr.sum()), 3))  # moving walls
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(B, S.SPH_F64, tol=1e-12, variant=S.SPH_CG, jacobi=jacobi, op_mode=op_mode)
+    Xo, ro, ho = O.cg_solve(oracle_op(w, jacobi=jacobi), B, tol=1e-12)
+    assert rep["status"] == S.SPH_OK and rep["state"] == [S.SPH_CONVERGED] * 3
+    assert abs(rep["iters"] - ro["iters"]) <= 1
+    assert rel_l2(X, Xo) < 1e-10
+    assert _walls_exact(w, X, B)
+    h = np.array(rep["history"])
+    n = min(len(h), len(ho), 6)
+    assert np.allclose(h[:n], ho[:n], rtol=1e-7, atol=0), np.abs(h[:n] / ho[:n] - 1).max()
+
+
+@pytest.mark.parametrize("prec", [S.SPH_F32, S.SPH_MIXED])
+@pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
+def test_cg_fp32_paths(ctx, prec, op_mode):
+    # FP32 vectors and operator (FP64 solution under SPH_MIXED), eps = 1e-6,
+    # against the oracle's CG at 1e-12: relative L2 below 1e-5
+    w = _uniform_mass(small_tank(seed=24, wall=W.WALL_DYNAMIC))
+    print(f"[cg32] {w.name} prec={prec} mode={op_mode}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, prec, tol=1e-6, variant=S.SPH_CG, op_mode=op_mode)
+    Xo, ro, _ = O.cg_solve(oracle_op(w), w.rhs, tol=1e-12)
+    assert rep["status"] == S.SPH_OK
+    assert rel_l2(X, Xo) < 1e-5
+    for c in range(3):
+        assert rep["true_rr"][c] < rep["tau2"][c] * 1.0001 or rep["bb"][c] == 0.0
+
+
+def test_cg_forced_stall_matches_oracle(ctx):
+    w = _uniform_mass(small_tank(seed=41, wall=W.WALL_DYNAMIC, dt_nu=30.0))
+    g = GpuCase(ctx, w)
+    X0, r0 = g.solve(w.rhs, S.SPH_F64, tol=1e-10, variant=S.SPH_CG)
+    X1, r1 = g.solve(w.rhs, S.SPH_F64, tol=1e-10, variant=S.SPH_CG, force_stall=(3, 1))
+    Xo, ro, _ = O.cg_solve(oracle_op(w), w.rhs, tol=1e-10, force_stall=(3, 1))
+    assert r0["stall_count"] == [0, 0, 0] and r1["stall_count"] == ro["stall_count"] == [0, 1, 0]
+    h0, h1 = np.array(r0["history"]), np.array(r1["history"])
+    n = min(len(h0), len(h1))
+    # the other components do not see the stall; the stalled one stands still
+    assert np.array_equal(h0[:n, 0], h1[:n, 0]) and np.array_equal(h0[:n, 2], h1[:n, 2])
+    assert h1[3, 1] == h1[2, 1]
+    assert abs(r1["iters"] - ro["iters"]) <= 1 and rel_l2(X1, Xo) < 1e-8
+
+
+def test_cg_true_residual_checks_match_oracle(ctx):
+    w = _uniform_mass(small_tank(seed=61, wall=W.WALL_DYNAMIC))
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F64, tol=1e-10, variant=S.SPH_CG, true_res_period=1)
+    Xo, ro, _ = O.cg_solve(oracle_op(w), w.rhs, tol=1e-10, true_res_period=1)
+    assert rep["n_replaced"] == 0 == ro["n_replaced"]
+    assert abs(rep["n_true_checks"] - ro["n_true_checks"]) <= 1
+    assert rel_l2(X, Xo) < 1e-9
+
+
+def test_cg_start_handling(ctx):
+    # a given start (wall rows replaced by their exact value), the exact
+    # solution as start (no iteration) and a zero right-hand side
+    w = _uniform_mass(small_tank(seed=62, wall=W.WALL_DYNAMIC))
+    g = GpuCase(ctx, w)
+    X0 = np.random.default_rng(3).normal(size=(w.n, 3))
+    X, rep = g.solve(w.rhs, S.SPH_F64, X0=X0, tol=1e-11, variant=S.SPH_CG)
+    Xo, ro, _ = O.cg_solve(oracle_op(w), w.rhs, X0=X0, tol=1e-11)
+    assert rep["status"] == 0 and abs(rep["iters"] - ro["iters"]) <= 1 and rel_l2(X, Xo) < 1e-10
+    assert _walls_exact(w, X, w.rhs)
+    Xd = O.dense_solve(oracle_op(w), w.rhs)
+    X2, rep2 = g.solve(w.rhs, S.SPH_F64, X0=Xd, tol=1e-8, variant=S.SPH_CG)
+    assert rep2["iters"] == 0
+    X3, rep3 = g.solve(np.zeros((w.n, 3)), S.SPH_F64, tol=1e-8, variant=S.SPH_CG)
+    assert rep3["iters"] == 0 and np.all(X3 == 0.0)
+
+
+def test_cg_rejects_dummy_walls(ctx):
+    w = small_tank(seed=63, wall=W.WALL_DUMMY)
+    g = GpuCase(ctx, w)
+    with pytest.raises(S.SphError) as e:
+        g.solve(w.rhs, S.SPH_F64, variant=S.SPH_CG)
+    assert e.value.status == S.SPH_E_ARG
+
+
+def test_cg_tank_100_fp32(ctx):
+    # the benchmark tank with dynamic walls (N = 1,157,308): FP32 CG to 1e-6
+    # from the previous-step start, checked on 2,048 sampled rows against
+    # the oracle's operator, and against the robust BiCGSTAB's solution of
+    # the same system (both at the same tolerance)
+    from test_gpu_configs import _check_solution, _rows
+    w = W.open_box(100, wall=W.WALL_DYNAMIC)
+    print(f"[cg tank] n={w.n}", flush=True)
+    g = GpuCase(ctx, w)
+    o = dict(history=False, true_res_period=20, restart_drop=-1.0)
+    X, rep = g.solve(w.rhs, S.SPH_F32, X0=w.x0, variant=S.SPH_CG, **o)
+    _check_solution(g, w, w.rhs, X, rep, _rows(w, 11), "cg tank100 f32")
+    assert _walls_exact(w, X, w.rhs)
+    Xb, repb = g.solve(w.rhs, S.SPH_F32, X0=w.x0, variant=S.SPH_ROBUST, **o)
+    X64, _ = g.solve(w.rhs, S.SPH_F64, X0=w.x0, tol=1e-10, variant=S.SPH_CG, **o)
+    e_cg, e_bi = rel_l2(X, X64), rel_l2(Xb, X64)
+    print(f"[cg tank] iterations CG {rep['iters']} BiCGSTAB {repb['iters']}; "
+          f"rel L2 to the FP64 1e-10 solve: CG {e_cg:.3e} BiCGSTAB {e_bi:.3e}", flush=True)
+    assert e_cg <= 2.0 * e_bi + 1e-6
