@@ -59,6 +59,10 @@ def lib():
         L.orc_cg.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.POINTER(dp), C.c_double, C.c_int32,
                              C.c_double, C.c_int32, C.c_int32, C.c_int32, C.POINTER(OrcReport), dp,
                              C.c_int32]
+        L.orc_ybar.restype = C.c_double
+        L.orc_ybar.argtypes = [C.c_double, C.c_double]
+        L.orc_papanastasiou.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.c_double, C.c_double, C.c_double,
+                                        dp, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -284,6 +288,23 @@ def cg_solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, floor=DBL_MIN, 
                   n_true_checks=rep.n_true_checks, n_replaced=rep.n_replaced,
                   history_len=rep.history_len)
     return np.stack(xs, axis=1), report, hist[:rep.history_len].copy()
+
+
+def ybar(D, m):
+    """The regularised yield term Ybar(D) of the Papanastasiou law (scalar)."""
+    return float(lib().orc_ybar(float(D), float(m)))
+
+
+def papanastasiou(op: Operator, U, tau0, m, mu0):
+    """Viscosity from the velocity field U (n, 3): returns (mu, D), mu updated
+    on fluid rows (tau0 Ybar(D) + mu0), the operator's own mu on wall rows."""
+    U = np.asarray(U, dtype=np.float64)
+    us = [np.ascontiguousarray(U[:, c]) for c in range(3)]
+    ua = (C.POINTER(C.c_double) * 3)(*[_dp(a) for a in us])
+    mu = np.zeros(op.n)
+    D = np.zeros(op.n)
+    lib().orc_papanastasiou(C.byref(op.s), ua, float(tau0), float(m), float(mu0), _dp(mu), _dp(D))
+    return mu, D
 
 
 def dense_solve(op: Operator, B):

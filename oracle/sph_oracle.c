@@ -25,6 +25,10 @@
  *     uniform mass)                               Section "Restructuring the Conjugate
  *                                                 Gradient", Section "Linear system
  *                                                 properties and resolution"
+ *   - the Papanastasiou viscosity from the velocity field: velocity gradient,
+ *     shear rate, its second invariant and the regularised yield term with
+ *     its truncated Maclaurin branch              Section "Non-Newtonian viscosity",
+ *                                                 eq. papa
  *
  * Readings of passages that are ambiguous or inconsistent in the paper:
  *   - Sign of K (eq. kab): the Wendland F is <= 0, so the printed K would be
@@ -66,6 +70,20 @@
  *   - CG stall: alpha = 0 in finite precision (or a zero or non-finite
  *     p.Ap) while r.r is above the threshold marks the component stalled;
  *     the iteration completes (a no-op update) and beta is taken as 0.
+ *   - velocity gradient: the printed sum, with r_ab = r_a - r_b and
+ *     u_ab = u_a - u_b over all neighbours a of b (fluid and wall, with the
+ *     velocities given for them), is minus the usual SPH gradient (F <= 0);
+ *     only its symmetric part enters D quadratically, so the sign does not
+ *     matter and the printed form is kept.
+ *   - second invariant: D = sqrt(2 S:S) with S the symmetric part, the norm
+ *     that equals the shear rate in simple shear (u = (G y, 0, 0) gives D = G
+ *     in the continuum), as the yield law needs.
+ *   - Maclaurin threshold: the printed switch "D >= m" cannot be meant (for
+ *     m = 1000 the 8-term series would run at m D up to 1e6); the branch is
+ *     taken for x = m D below x0 = (9! 2^-23)^(1/8) = 0.675..., where the
+ *     first omitted term x^8/9! equals single-precision epsilon, the
+ *     accuracy the paper states for its choice.
+ *   - wall particles keep their given viscosity; only fluid rows are updated.
  */
 #include <math.h>
 #include <stdint.h>
@@ -948,4 +966,57 @@ int orc_cg(const orc_op *op, const double *const *b, double *const *x, double to
     rep->status = any_prog ? ORC_NOT_CONVERGED : (any_stall ? ORC_STATUS_STALLED : ORC_OK);
     free(buf);
     return rep->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Papanastasiou viscosity (Section "Non-Newtonian viscosity", eq. papa).    */
+/* ------------------------------------------------------------------------ */
+
+/* Ybar(D) = (1 - exp(-m D))/D for m D >= x0, else m T(m D) with T the
+ * Maclaurin series of (1 - e^-x)/x truncated after 8 terms, in Horner form:
+ * T(x) = 1 - x/2 (1 - x/3 (1 - x/4 (1 - x/5 (1 - x/6 (1 - x/7 (1 - x/8)))))). */
+double orc_ybar(double D, double m) {
+    const double x0 = pow(362880.0 * ldexp(1.0, -23), 0.125);
+    double x = m * D;
+    if (x >= x0) return (1.0 - exp(-x)) / D;
+    double t = 1.0;
+    for (int k = 8; k >= 2; --k) t = 1.0 - x / (double)k * t;
+    return m * t;
+}
+
+/* Per particle b: G = sum_a (m_a/rho_a) F(r_ab) r_ab u_ab^T (r_ab = r_a - r_b
+ * by minimum image, u_ab = u_a - u_b), S = (G + G^T)/2, D_b = sqrt(2 S:S);
+ * fluid rows: mu_b = tau0 Ybar(D_b) + mu0, wall rows keep op->mu.  u: three
+ * component arrays; D_out may be NULL. */
+void orc_papanastasiou(const orc_op *op, const double *const *u, double tau0, double m, double mu0,
+                       double *mu_out, double *D_out) {
+    const double h = op->h;
+    const double h5 = h * h * h * h * h;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < op->n; ++b) {
+        double G[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+            int64_t a = op->cols[k];
+            double r[3];
+            r[0] = orc_disp(op->x[a], op->x[b], op->period[0]);
+            r[1] = orc_disp(op->y[a], op->y[b], op->period[1]);
+            r[2] = orc_disp(op->z[a], op->z[b], op->period[2]);
+            double d = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+            double F = orc_wendland_f(d / h) / h5;
+            double vf = op->mass[a] / op->rho[a] * F;
+            double du[3];
+            for (int j = 0; j < 3; ++j) du[j] = u[j][a] - u[j][b];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) G[i][j] += vf * r[i] * du[j];
+        }
+        double ss = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double sij = 0.5 * (G[i][j] + G[j][i]);
+                ss += sij * sij;
+            }
+        double D = sqrt(2.0 * ss);
+        if (D_out) D_out[b] = D;
+        mu_out[b] = op->type[b] == ORC_FLUID ? tau0 * orc_ybar(D, m) + mu0 : op->mu[b];
+    }
 }
