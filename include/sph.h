@@ -18,9 +18,10 @@
  *   - Pointers inside sph_particles and the x/y/rhs arrays are DEVICE pointers
  *     owned by the caller, in the caller's (original) particle order, unless
  *     the comment says "host".  The library never frees them.
- *   - Work is issued on the context's HIP stream.  sph_visc_apply is
- *     asynchronous; sph_build_neighbors, sph_neighbors_export and
- *     sph_visc_solve return after the stream work they issued has finished.
+ *   - Work is issued on the context's HIP stream.  sph_visc_apply and
+ *     sph_visc_papanastasiou are asynchronous; sph_build_neighbors,
+ *     sph_neighbors_export and sph_visc_solve return after the stream work
+ *     they issued has finished.
  *   - Negative status = failure, outputs undefined.  Positive status = the
  *     outputs are valid and the report says why the solve stopped.
  *   - A context is not thread-safe; use one context per host thread.
@@ -249,6 +250,27 @@ sph_status sph_visc_solve(sph_ctx *ctx, const sph_nbr *nb, const sph_domain *dom
                           const sph_particles *p, const sph_visc_params *params, int32_t prec,
                           const void *const rhs[3], void *const x[3], const sph_solve_opts *opts,
                           sph_solve_report *report);
+
+/* Apparent viscosity of the Papanastasiou regularised Bingham law from a
+ * velocity field (Section "Non-Newtonian viscosity", eq. papa), the update
+ * the paper makes between solves with the viscosity lagged one step:
+ *   G_b   = sum_a (m_a / rho_a) F(r_ab) r_ab u_ab^T over the neighbours a of
+ *           b (fluid and wall, with the velocities given for them), r_ab =
+ *           r_a - r_b by minimum image, u_ab = u_a - u_b, F as in eq. kab;
+ *   S_b   = (G_b + G_b^T) / 2, D_b = sqrt(2 S_b : S_b) (equal to the rate in
+ *           simple shear);
+ *   mu_b  = tau0 Ybar(D_b) + mu0 on fluid rows, Ybar(D) = (1 - e^{-m D}) / D,
+ *           replaced for m D < (9! 2^-23)^(1/8) = 0.675 by m times its
+ *           Maclaurin series cut after 8 terms (Horner form), the D -> 0
+ *           limit being m; wall rows keep p->mu.
+ * Everything in FP64.  u[c]: device, n values of precision prec (SPH_F64 or
+ * SPH_F32), caller order.  mu_out: device, n doubles, caller order; may be
+ * p->mu itself (updated in place).  shear_out: device, n doubles receiving
+ * D, or null.  tau0, mu0 finite and >= 0, m finite and > 0, else SPH_E_ARG.
+ * Asynchronous on the context stream, like sph_visc_apply. */
+sph_status sph_visc_papanastasiou(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p, int32_t prec,
+                                  const void *const u[3], double tau0, double m, double mu0,
+                                  double *mu_out, double *shear_out);
 
 /* ------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper, which names better initial

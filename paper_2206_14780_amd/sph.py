@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     L.sph_visc_apply.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp), P(_vp)]
     L.sph_visc_solve.argtypes = [_vp, _vp, P(sph_domain), P(sph_particles), P(sph_visc_params), i32,
                                  P(_vp), P(_vp), P(sph_solve_opts), P(sph_solve_report)]
+    L.sph_visc_papanastasiou.argtypes = [_vp, _vp, P(sph_particles), i32, P(_vp), C.c_double, C.c_double,
+                                         C.c_double, _vp, _vp]
     L.sph_mlp_samples.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), P(_vp), P(_vp),
                                   P(_vp), _vp, P(C.c_double)]
     L.sph_mlp_warmstart.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp),
@@ -112,8 +114,8 @@ def load(path: str = LIB_PATH):
                                      P(C.c_double)]
     for f in ("sph_create", "sph_destroy", "sph_set_stream", "sph_build_neighbors",
               "sph_neighbors_info", "sph_neighbors_export", "sph_neighbors_free", "sph_visc_apply",
-              "sph_visc_solve", "sph_mlp_samples", "sph_mlp_warmstart", "sph_mlp_forward",
-              "sph_mlp_grad", "sph_mlp_train_step"):
+              "sph_visc_solve", "sph_visc_papanastasiou", "sph_mlp_samples", "sph_mlp_warmstart",
+              "sph_mlp_forward", "sph_mlp_grad", "sph_mlp_train_step"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -256,6 +258,16 @@ class Context:
         pc = particles.c()
         self._check(self.L.sph_visc_apply(self.h, nb.h, C.byref(pc), C.byref(params), int(prec), xs,
                                           ys), "sph_visc_apply")
+
+    # --- sph_visc_papanastasiou ---------------------------------------------
+    def sph_visc_papanastasiou(self, nb: "Neighbors", particles: Particles, prec: int, u: Sequence,
+                               tau0: float, m: float, mu0: float, mu_out, shear_out=None):
+        us = (C.c_void_p * 3)(*[_ptr(t) for t in u])
+        pc = particles.c()
+        self._check(self.L.sph_visc_papanastasiou(self.h, nb.h, C.byref(pc), int(prec), us, float(tau0),
+                                                  float(m), float(mu0), _ptr(mu_out),
+                                                  None if shear_out is None else _ptr(shear_out)),
+                    "sph_visc_papanastasiou")
 
     # --- sph_visc_solve -----------------------------------------------------
     def sph_visc_solve(self, nb: Optional["Neighbors"], domain: Optional[sph_domain],
