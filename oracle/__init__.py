@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 CONVERGED, STALLED, PROGRESSING = 0, 1, 2
 ROBUST, STANDARD = 0, 1
+FLUID_TYPE = 0  # particle type of fluid rows (every other type is a wall)
 FLT_MIN = float(np.finfo(np.float32).tiny)
 DBL_MIN = float(np.finfo(np.float64).tiny)
 
