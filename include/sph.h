@@ -272,6 +272,44 @@ sph_status sph_visc_papanastasiou(sph_ctx *ctx, const sph_nbr *nb, const sph_par
                                   const void *const u[3], double tau0, double m, double mu0,
                                   double *mu_out, double *shear_out);
 
+/* Parameters of one semi-implicit step (sph_semi_implicit_step). */
+typedef struct {
+    double g[3];           /* body force per unit mass: the inviscid acceleration of this path */
+    int32_t papanastasiou; /* 1 = update the fluid viscosity with the law of sph_visc_papanastasiou */
+    double tau0, m, mu0;   /* its parameters (read when papanastasiou = 1) */
+} sph_step_params;
+
+/* One step of the semi-implicit predictor/corrector (Section "Semi-implicit
+ * integration scheme") with the body force as the whole inviscid
+ * acceleration and the density held fixed (pressure and continuity belong to
+ * the weakly compressible solver around this one):
+ *   half step: A(r^n, mu^n; dt/2) V* = u^n + (dt/2) g, started from u^n;
+ *              u* = V* on fluid rows; r* = r^n + (dt/2) u^n; mu* = mu(r*, u*)
+ *   full step: A(r*, mu*; dt) V = u^n + dt g, started from u*;
+ *              u^{n+1} = V on fluid rows; r^{n+1} = r^n + (dt/2)(u^n + u^{n+1});
+ *              mu^{n+1} = mu(r^{n+1}, u^{n+1})  (the viscosity lags one step)
+ * Wall particles keep their position and velocity (u on wall rows is the
+ * prescribed wall velocity u_w; their right-hand side is u_w for dynamic and
+ * 2 u_w for dummy walls) and their viscosity.  Positions are wrapped into
+ * the box on periodic axes.  The neighbour lists are rebuilt at r^n, r* and
+ * (with the viscosity update) r^{n+1}.
+ *   p: positions, mass, rho, mu and type at step n (device, caller order).
+ *   params: dt = the full step; wall, avg, jacobi, op_mode as for a solve.
+ *   prec: SPH_F64 or SPH_MIXED (the velocities are FP64 arrays).
+ *   opts: options of both solves (x0_given and the learned start are set by
+ *         the step: each solve starts from the previous velocity).
+ *   pos_out[c]: device, n doubles: r^{n+1}; may be p->x, p->y, p->z.
+ *   u[c]: device, n doubles: u^n on entry, u^{n+1} on exit.
+ *   mu_out: device, n doubles: mu^{n+1} (a copy of p->mu without the
+ *         update); may be p->mu.
+ *   reports: host, two reports (half step, full step) or null.
+ * Returns after the step's work has finished; the status is the worse of
+ * the two solves' (negative on failure, when the outputs are undefined). */
+sph_status sph_semi_implicit_step(sph_ctx *ctx, const sph_domain *dom, const sph_particles *p,
+                                  const sph_visc_params *params, int32_t prec, const sph_step_params *sp,
+                                  const sph_solve_opts *opts, double *const pos_out[3], double *const u[3],
+                                  double *mu_out, sph_solve_report *reports);
+
 /* ------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper, which names better initial
  * guesses as future work (Sections "Conclusions and future work" and

@@ -193,7 +193,7 @@ enum Slot : int {
     kVecB, kVecX, kVecR, kVecRh0, kVecP, kVecAp, kVecS, kVecAs, kVecTmp, kB64,
     kPartA1, kPartA2, kPartK3, kPartChk, kCtl, kHist, kStallHist, kScanTmp,
     kApplyIn, kApplyOut, kExportCnt, kNnzCount, kMlpPart, kMlpOut, kWarmS, kWarmO, kWarmInfo, kWarmPart,
-    kWarmPart2, kWarmU, kList, kWList, kNbrCell, kNbrCount, kNbrFill, kViscU, kNumSlots
+    kWarmPart2, kWarmU, kList, kWList, kNbrCell, kNbrCount, kNbrFill, kViscU, kStepBuf, kNumSlots
 };
 
 }  // namespace sph

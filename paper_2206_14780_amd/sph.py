@@ -53,6 +53,22 @@ class sph_solve_opts(C.Structure):
                 ("restart_drop", C.c_double), ("warm_params", _vp), ("warm_u", _vp * 3)]
 
 
+class sph_step_params(C.Structure):
+    _fields_ = [("g", C.c_double * 3), ("papanastasiou", C.c_int32), ("tau0", C.c_double), ("m", C.c_double),
+                ("mu0", C.c_double)]
+
+
+def make_step_params(g, papa=None) -> sph_step_params:
+    """Body force g (3,) and papa = (tau0, m, mu0) or None (viscosity kept)."""
+    sp = sph_step_params()
+    for c in range(3):
+        sp.g[c] = float(g[c])
+    if papa is not None:
+        sp.papanastasiou = 1
+        sp.tau0, sp.m, sp.mu0 = (float(v) for v in papa)
+    return sp
+
+
 class sph_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("state", C.c_int32 * 3),
                 ("stall_count", C.c_int32 * 3), ("rr", C.c_double * 3), ("bb", C.c_double * 3),
@@ -104,6 +120,9 @@ def load(path: str = LIB_PATH):
                                  P(_vp), P(_vp), P(sph_solve_opts), P(sph_solve_report)]
     L.sph_visc_papanastasiou.argtypes = [_vp, _vp, P(sph_particles), i32, P(_vp), C.c_double, C.c_double,
                                          C.c_double, _vp, _vp]
+    L.sph_semi_implicit_step.argtypes = [_vp, P(sph_domain), P(sph_particles), P(sph_visc_params), i32,
+                                         P(sph_step_params), P(sph_solve_opts), P(_vp), P(_vp), _vp,
+                                         P(sph_solve_report)]
     L.sph_mlp_samples.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), P(_vp), P(_vp),
                                   P(_vp), _vp, P(C.c_double)]
     L.sph_mlp_warmstart.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp),
@@ -114,7 +133,8 @@ def load(path: str = LIB_PATH):
                                      P(C.c_double)]
     for f in ("sph_create", "sph_destroy", "sph_set_stream", "sph_build_neighbors",
               "sph_neighbors_info", "sph_neighbors_export", "sph_neighbors_free", "sph_visc_apply",
-              "sph_visc_solve", "sph_visc_papanastasiou", "sph_mlp_samples", "sph_mlp_warmstart",
+              "sph_visc_solve", "sph_visc_papanastasiou", "sph_semi_implicit_step", "sph_mlp_samples",
+              "sph_mlp_warmstart",
               "sph_mlp_forward", "sph_mlp_grad", "sph_mlp_train_step"):
         getattr(L, f).restype = st
     _lib = L
@@ -297,6 +317,22 @@ class Context:
         if history_cap > 0:
             out["history"] = [[hist[3 * i + c] for c in range(3)] for i in range(rep.history_len)]
         return out
+
+    # --- sph_semi_implicit_step ---------------------------------------------
+    def sph_semi_implicit_step(self, domain: sph_domain, particles: Particles, params: sph_visc_params,
+                               prec: int, step: sph_step_params, opts: sph_solve_opts, pos_out: Sequence,
+                               u: Sequence, mu_out) -> list:
+        """One predictor/corrector step; returns the two solve reports
+        (half step, full step) as dicts with iters, status and times."""
+        ps = (C.c_void_p * 3)(*[_ptr(t) for t in pos_out])
+        us = (C.c_void_p * 3)(*[_ptr(t) for t in u])
+        reps = (sph_solve_report * 2)()
+        pc = particles.c()
+        st = self.L.sph_semi_implicit_step(self.h, C.byref(domain), C.byref(pc), C.byref(params), int(prec),
+                                           C.byref(step), C.byref(opts), ps, us, _ptr(mu_out), reps)
+        self._check(st, "sph_semi_implicit_step", soft_ok=True)
+        return [dict(status=r.status, iters=r.iters, state=list(r.state), true_rr=list(r.true_rr),
+                     bb=list(r.bb), setup_ms=r.setup_ms, iterate_ms=r.iterate_ms) for r in reps]
 
 
     # --- learned initial guess ----------------------------------------------
