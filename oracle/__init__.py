@@ -23,6 +23,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 CONVERGED, STALLED, PROGRESSING = 0, 1, 2
 ROBUST, STANDARD = 0, 1
 FLUID_TYPE = 0  # particle type of fluid rows (every other type is a wall)
+KERNEL_WENDLAND, KERNEL_GAUSSIAN = 0, 1
+SUPPORT = {KERNEL_WENDLAND: 2.0, KERNEL_GAUSSIAN: 3.0}  # support radius in units of h
 FLT_MIN = float(np.finfo(np.float32).tiny)
 DBL_MIN = float(np.finfo(np.float64).tiny)
 
@@ -41,6 +43,9 @@ def lib():
         L.orc_wendland_w.argtypes = [C.c_double]
         L.orc_wendland_f.restype = C.c_double
         L.orc_wendland_f.argtypes = [C.c_double]
+        for f in ("orc_gauss_w", "orc_gauss_f"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double]
         L.orc_neighbors_brute.restype = C.c_int64
         L.orc_neighbors_brute.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, i64p, i32p, C.c_int64]
         L.orc_neighbors_grid.restype = C.c_int64
@@ -78,7 +83,7 @@ class OrcOp(C.Structure):
                 ("mass", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
                 ("mu", C.POINTER(C.c_double)), ("type", C.POINTER(C.c_uint8)),
                 ("dt", C.c_double), ("wall", C.c_int32), ("avg", C.c_int32),
-                ("jacobi", C.c_int32)]
+                ("jacobi", C.c_int32), ("kernel", C.c_int32)]
 
 
 class OrcReport(C.Structure):
@@ -115,28 +120,38 @@ def wendland_f(q):
     return np.vectorize(L.orc_wendland_f, otypes=[np.float64])(q)
 
 
+def gauss_w(q):
+    """w(q) of the normalised truncated Gaussian (radius 3), elementwise."""
+    return np.vectorize(lib().orc_gauss_w, otypes=[np.float64])(np.asarray(q, dtype=np.float64))
+
+
+def gauss_f(q):
+    """f(q) = w'(q)/q of the truncated Gaussian, elementwise."""
+    return np.vectorize(lib().orc_gauss_f, otypes=[np.float64])(np.asarray(q, dtype=np.float64))
+
+
 def _soa(pos):
     pos = np.asarray(pos, dtype=np.float64)
     return [np.ascontiguousarray(pos[:, a]) for a in range(3)]
 
 
-def neighbors(pos, period, h, lo=None, method="grid"):
+def neighbors(pos, period, h, lo=None, method="grid", support=2.0):
     """CSR neighbour lists (row_ptr int64 [n+1], cols int32 ascending) of
-    N(i) = {j != i : |r_i - r_j|^2 < (2h)^2}, minimum image on axes whose
-    period is > 0.  method = "brute" (all pairs) or "grid" (cell grid)."""
+    N(i) = {j != i : |r_i - r_j|^2 < (support h)^2}, minimum image on axes
+    whose period is > 0.  method = "brute" (all pairs) or "grid" (cell grid)."""
     L = lib()
     x, y, z = _soa(pos)
     n = x.shape[0]
     per = np.ascontiguousarray(np.asarray(period, dtype=np.float64))
     lo_ = np.ascontiguousarray(np.zeros(3) if lo is None else np.asarray(lo, dtype=np.float64))
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    cap = max(1, n * 96)
+    cap = max(1, n * (96 if support <= 2.0 else 300))
     while True:
         cols = np.zeros(cap, dtype=np.int32)
         args = [n, _dp(x), _dp(y), _dp(z)]
         if method == "grid":
             args.append(_dp(lo_))
-        args += [_dp(per), float(h), row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+        args += [_dp(per), float(support) * float(h), row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
                  cols.ctypes.data_as(C.POINTER(C.c_int32)), cap]
         fn = L.orc_neighbors_grid if method == "grid" else L.orc_neighbors_brute
         nnz = int(fn(*args))
@@ -145,7 +160,7 @@ def neighbors(pos, period, h, lo=None, method="grid"):
         cap = nnz
 
 
-def neighbors_rows(pos, period, h, rows, lo=None):
+def neighbors_rows(pos, period, h, rows, lo=None, support=2.0):
     """CSR lists (row_ptr int64 [n+1], cols int32 ascending) holding the
     neighbour set of `rows` only (every other row empty): the cell-grid search
     of `neighbors` restricted to a sample of rows, so that an Operator built
@@ -159,10 +174,11 @@ def neighbors_rows(pos, period, h, rows, lo=None):
     per = np.ascontiguousarray(np.asarray(period, dtype=np.float64))
     lo_ = np.ascontiguousarray(np.zeros(3) if lo is None else np.asarray(lo, dtype=np.float64))
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    cap = max(1, rows.size * 128)
+    cap = max(1, rows.size * (128 if support <= 2.0 else 320))
     while True:
         cols = np.zeros(cap, dtype=np.int32)
-        nnz = int(L.orc_neighbors_grid_rows(n, _dp(x), _dp(y), _dp(z), _dp(lo_), _dp(per), float(h),
+        nnz = int(L.orc_neighbors_grid_rows(n, _dp(x), _dp(y), _dp(z), _dp(lo_), _dp(per),
+                                            float(support) * float(h),
                                             rows.ctypes.data_as(C.POINTER(C.c_int64)), rows.size,
                                             row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
                                             cols.ctypes.data_as(C.POINTER(C.c_int32)), cap))
@@ -176,13 +192,14 @@ class Operator:
     scaled), backed by the C oracle.  Keeps every array it hands to C alive."""
 
     def __init__(self, pos, mass, rho, mu, ptype, period, h, dt, wall, avg, jacobi=True,
-                 nbr=None, lo=None):
+                 nbr=None, lo=None, kernel=KERNEL_WENDLAND):
         pos = np.asarray(pos, dtype=np.float64)
         self.n = pos.shape[0]
         self.period = np.asarray(period, dtype=np.float64)
         self.h = float(h)
+        self.kernel = int(kernel)
         if nbr is None:
-            nbr = neighbors(pos, self.period, h, lo=lo, method="grid")
+            nbr = neighbors(pos, self.period, h, lo=lo, method="grid", support=SUPPORT[self.kernel])
         self.row_ptr, self.cols = nbr
         self._x, self._y, self._z = _soa(pos)
         self._mass = np.ascontiguousarray(np.broadcast_to(np.asarray(mass, np.float64), (self.n,)))
@@ -203,13 +220,14 @@ class Operator:
         s.wall = int(wall)
         s.avg = int(avg)
         s.jacobi = int(bool(jacobi))
+        s.kernel = self.kernel
         self.s = s
         self.dt, self.wall, self.avg, self.jacobi = float(dt), int(wall), int(avg), bool(jacobi)
 
     @classmethod
     def from_workload(cls, w, jacobi=True, nbr=None, **over):
         kw = dict(pos=w.pos, mass=w.mass, rho=w.rho, mu=w.mu, ptype=w.ptype, period=w.period,
-                  h=w.h, dt=w.dt, wall=w.wall, avg=w.avg)
+                  h=w.h, dt=w.dt, wall=w.wall, avg=w.avg, kernel=getattr(w, "kernel", KERNEL_WENDLAND))
         kw.update(over)
         return cls(jacobi=jacobi, nbr=nbr, lo=w.lo, **kw)
 

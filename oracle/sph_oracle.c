@@ -9,7 +9,8 @@
  * pitfalls (fused multiply-add) requires.
  *
  * Contents, each citing the passage it follows:
- *   - Wendland psi_{3,1} kernel w(q), f(q)       Section "Smoothing kernel choice"
+ *   - Wendland psi_{3,1} kernel w(q), f(q) and the truncated Gaussian (k = 3)
+ *                                                 Section "Smoothing kernel choice"
  *   - neighbour sets: brute force and a cell grid Section "Smoothing kernel choice"
  *                                                 (support radius 2h), appendix on
  *                                                 relative positions (minimum image)
@@ -148,6 +149,29 @@ double orc_wendland_f(double q) {
     return 105.0 / (128.0 * ORC_PI) * (a * a * a);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Normalised truncated Gaussian of radius k = 3 (Section "Smoothing kernel  */
+/* choice"):  w(q) = (e^{-q^2} - e^{-k^2}) / w_G for q < k, with            */
+/*   w_G = pi^{3/2} erf(k) - (2 pi/3) e^{-k^2} k (3 + 2 k^2),               */
+/* and f(q) = w'(q)/q = -2 e^{-q^2} / w_G for q < k (the printed f has the  */
+/* opposite sign; F = (1/r) dW/dr is kept, as for the Wendland kernel).     */
+/* ------------------------------------------------------------------------ */
+#define ORC_GAUSS_K 3.0
+static double orc_gauss_norm(void) {
+    const double k = ORC_GAUSS_K;
+    return pow(ORC_PI, 1.5) * erf(k) - 2.0 * ORC_PI / 3.0 * exp(-k * k) * k * (3.0 + 2.0 * k * k);
+}
+
+double orc_gauss_w(double q) {
+    if (!(q < ORC_GAUSS_K)) return 0.0;
+    return (exp(-q * q) - exp(-ORC_GAUSS_K * ORC_GAUSS_K)) / orc_gauss_norm();
+}
+
+double orc_gauss_f(double q) {
+    if (!(q < ORC_GAUSS_K)) return 0.0;
+    return -2.0 * exp(-q * q) / orc_gauss_norm();
+}
+
 /* Displacement r_i - r_j on one axis, minimum image when the axis is periodic. */
 static double orc_disp(double xi, double xj, double period) {
     double d = xi - xj;
@@ -169,14 +193,14 @@ static double orc_dist2(const double *x, const double *y, const double *z, int64
 }
 
 /* ------------------------------------------------------------------------ */
-/* Neighbour sets N(i) = { j != i : |r_i - r_j|^2 < (2h)^2 }.                  */
+/* Neighbour sets N(i) = { j != i : |r_i - r_j|^2 < s^2 }, s the kernel's     */
+/* support radius (2h Wendland, 3h Gaussian).                                 */
 /* CSR by row, columns ascending.  Returns total nnz; cols is written only     */
 /* up to `cap` entries (the caller re-calls with enough room).                */
 /* ------------------------------------------------------------------------ */
 int64_t orc_neighbors_brute(int64_t n, const double *x, const double *y, const double *z,
-                            const double *period, double h, int64_t *row_ptr, int32_t *cols,
+                            const double *period, double s, int64_t *row_ptr, int32_t *cols,
                             int64_t cap) {
-    double s = 2.0 * h;
     double cut2 = s * s;
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     #pragma omp parallel for schedule(static)
@@ -232,7 +256,7 @@ static int orc_cell_axis(double v, double org, double cs, int nc, int periodic) 
 }
 
 static void orc_grid_build(orc_grid *g, int64_t n, const double *x, const double *y,
-                           const double *z, const double *lo, const double *period, double h) {
+                           const double *z, const double *lo, const double *period, double s) {
     const double *p[3] = {x, y, z};
     for (int a = 0; a < 3; ++a) {
         double ext;
@@ -248,7 +272,7 @@ static void orc_grid_build(orc_grid *g, int64_t n, const double *x, const double
             g->org[a] = mn;
             ext = mx - mn;
         }
-        int nc = (int)floor(ext / (2.0 * h));
+        int nc = (int)floor(ext / s);
         if (nc < 1) nc = 1;
         if (period[a] <= 0.0 && ext <= 0.0) ext = 1.0;
         g->nc[a] = nc;
@@ -312,11 +336,10 @@ static int orc_grid_stencil(const orc_grid *g, int64_t c, const double *period, 
 }
 
 int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y, const double *z,
-                           const double *lo, const double *period, double h, int64_t *row_ptr,
+                           const double *lo, const double *period, double s, int64_t *row_ptr,
                            int32_t *cols, int64_t cap) {
     orc_grid g;
-    orc_grid_build(&g, n, x, y, z, lo, period, h);
-    double s = 2.0 * h;
+    orc_grid_build(&g, n, x, y, z, lo, period, s);
     double cut2 = s * s;
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     #pragma omp parallel for schedule(static)
@@ -358,12 +381,11 @@ int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y, const do
  * of single rows of systems too large for full lists.  rows[] ascending and
  * distinct, each in [0, n); row_ptr has n + 1 entries. */
 int64_t orc_neighbors_grid_rows(int64_t n, const double *x, const double *y, const double *z,
-                                const double *lo, const double *period, double h,
+                                const double *lo, const double *period, double s,
                                 const int64_t *rows, int64_t nrows, int64_t *row_ptr,
                                 int32_t *cols, int64_t cap) {
     orc_grid g;
-    orc_grid_build(&g, n, x, y, z, lo, period, h);
-    double s = 2.0 * h;
+    orc_grid_build(&g, n, x, y, z, lo, period, s);
     double cut2 = s * s;
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     #pragma omp parallel for schedule(dynamic, 16)
@@ -418,7 +440,18 @@ typedef struct {
     int32_t wall;   /* ORC_WALL_DYNAMIC / ORC_WALL_DUMMY */
     int32_t avg;    /* ORC_AVG_ARITH / ORC_AVG_HARMONIC */
     int32_t jacobi; /* 1: rows scaled by 1/A_bb (appendix "Implementation notes") */
+    int32_t kernel; /* ORC_KERNEL_WENDLAND / ORC_KERNEL_GAUSSIAN */
 } orc_op;
+
+#define ORC_KERNEL_WENDLAND 0
+#define ORC_KERNEL_GAUSSIAN 1
+
+static double orc_kernel_w(const orc_op *op, double q) {
+    return op->kernel == ORC_KERNEL_GAUSSIAN ? orc_gauss_w(q) : orc_wendland_w(q);
+}
+static double orc_kernel_f(const orc_op *op, double q) {
+    return op->kernel == ORC_KERNEL_GAUSSIAN ? orc_gauss_f(q) : orc_wendland_f(q);
+}
 
 /* 2 * mubar_ab: arithmetic mean (mu_a + mu_b)/2 or harmonic 2 mu_a mu_b/(mu_a + mu_b)
  * (Section "Discretized equations"). */
@@ -436,7 +469,7 @@ static double orc_pair_w(const orc_op *op, int64_t b, int64_t a) {
     double r2 = orc_dist2(op->x, op->y, op->z, b, a, op->period, 0, 0, 0);
     double q = sqrt(r2) / op->h;
     double h2 = op->h * op->h;
-    double F = orc_wendland_f(q) / (h2 * h2 * op->h);
+    double F = orc_kernel_f(op, q) / (h2 * h2 * op->h);
     double tm = orc_two_mubar(op->mu[a], op->mu[b], op->avg);
     return -(tm * op->mass[a] * F) / (op->rho[a] * op->rho[b]);
 }
@@ -445,7 +478,7 @@ static double orc_pair_w(const orc_op *op, int64_t b, int64_t a) {
 static double orc_pair_W(const orc_op *op, int64_t b, int64_t a) {
     double r2 = orc_dist2(op->x, op->y, op->z, b, a, op->period, 0, 0, 0);
     double q = sqrt(r2) / op->h;
-    return orc_wendland_w(q) / (op->h * op->h * op->h);
+    return orc_kernel_w(op, q) / (op->h * op->h * op->h);
 }
 
 /* Diagonal A_bb: 1 + dt sum_a w_ba for fluid rows (eq. diag), 1 for wall rows. */
@@ -1002,7 +1035,7 @@ void orc_papanastasiou(const orc_op *op, const double *const *u, double tau0, do
             r[1] = orc_disp(op->y[a], op->y[b], op->period[1]);
             r[2] = orc_disp(op->z[a], op->z[b], op->period[2]);
             double d = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
-            double F = orc_wendland_f(d / h) / h5;
+            double F = orc_kernel_f(op, d / h) / h5;
             double vf = op->mass[a] / op->rho[a] * F;
             double du[3];
             for (int j = 0; j < 3; ++j) du[j] = u[j][a] - u[j][b];

@@ -27,6 +27,8 @@ WALL_DUMMY = 1
 
 AVG_ARITH = 0
 AVG_HARMONIC = 1
+KERNEL_WENDLAND = 0
+KERNEL_GAUSSIAN = 1
 
 
 @dataclass
@@ -60,6 +62,7 @@ class Workload:
     x0: Optional[np.ndarray]
     tol: float
     meta: dict = field(default_factory=dict)
+    kernel: int = 0  # KERNEL_WENDLAND (support 2h) or KERNEL_GAUSSIAN (support 3h)
 
     @property
     def n(self) -> int:
