@@ -67,6 +67,14 @@ typedef enum {
  * tolerances with the FP32 operator. */
 enum { SPH_F64 = 0, SPH_F32 = 1, SPH_MIXED = 2 };
 enum { SPH_FLUID = 0, SPH_WALL = 1 };              /* particle type */
+/* Smoothing kernel (Section "Smoothing kernel choice"): the Wendland psi_{3,1}
+ * of radius 2, or the normalised truncated Gaussian of radius 3,
+ * w(q) = (e^{-q^2} - e^{-9}) / w_G with w_G = pi^{3/2} erf(3) - 2 pi e^{-9} 21/3
+ * and F = (1/r) dW/dr = -2 e^{-q^2} / (w_G h^5) (the printed f has the
+ * opposite sign; the derivative's is used, as for the Wendland kernel).  It is
+ * chosen with the domain of the neighbour build and holds for every operator,
+ * solve and viscosity update on that handle. */
+enum { SPH_KERNEL_WENDLAND = 0, SPH_KERNEL_GAUSSIAN = 1 };
 enum { SPH_WALL_DYNAMIC = 0, SPH_WALL_DUMMY = 1 }; /* boundary model (Section "Boundary conditions") */
 enum { SPH_AVG_ARITH = 0, SPH_AVG_HARMONIC = 1 };  /* pairwise viscosity mean (Section "Discretized equations") */
 enum { SPH_ROBUST = 0, SPH_STANDARD = 1, SPH_CG = 2 }; /* solver: robust / textbook BiCGSTAB, rotated CG */
@@ -88,7 +96,8 @@ typedef struct {
 typedef struct {
     double lo[3], hi[3];
     int32_t periodic[3];
-    double h; /* smoothing length; support radius 2h */
+    double h;       /* smoothing length */
+    int32_t kernel; /* SPH_KERNEL_WENDLAND (support 2h) or SPH_KERNEL_GAUSSIAN (support 3h) */
 } sph_domain;
 
 /* Parameters of A(dt).

@@ -229,7 +229,14 @@ using namespace sph;
 
 static sph_status make_grid(sph_ctx* ctx, const sph_domain* dom, Grid* g, int64_t* ncell) {
     if (!(dom->h > 0.0) || !std::isfinite(dom->h)) return ctx->fail(SPH_E_ARG, "domain: h must be > 0");
-    const double s = 2.0 * dom->h;
+    if (dom->kernel != SPH_KERNEL_WENDLAND && dom->kernel != SPH_KERNEL_GAUSSIAN)
+        return ctx->fail(SPH_E_ARG, "domain: kernel");
+    g->kernel = dom->kernel;
+    // support radius: 2h (Wendland) or k h with k = 3 (truncated Gaussian)
+    const double s = (dom->kernel == SPH_KERNEL_GAUSSIAN ? kGaussK : 2.0) * dom->h;
+    g->gauss_tail = std::exp(-kGaussK * kGaussK);
+    g->gauss_norm = std::pow(kPi, 1.5) * std::erf(kGaussK) -
+                    2.0 * kPi / 3.0 * std::exp(-kGaussK * kGaussK) * kGaussK * (3.0 + 2.0 * kGaussK * kGaussK);
     g->h = dom->h;
     g->cut2 = s * s;
     g->inv_h = 1.0 / dom->h;
@@ -241,7 +248,7 @@ static sph_status make_grid(sph_ctx* ctx, const sph_domain* dom, Grid* g, int64_
         if (!std::isfinite(L) || !(L >= 0.0)) return ctx->fail(SPH_E_ARG, "domain: hi < lo");
         g->per[a] = dom->periodic[a] ? 1 : 0;
         g->org[a] = dom->lo[a];
-        // cells a hair wider than 2h, so that rounding in the binning can never
+        // cells a hair wider than the support, so that rounding in the binning can never
         // separate two neighbours by more than one cell
         double target = s * (1.0 + 1e-9);
         int64_t nc = (int64_t)std::floor(L / target);

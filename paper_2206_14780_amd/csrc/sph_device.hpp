@@ -22,6 +22,27 @@ __device__ inline double wendland_f(double q) {
     return 105.0 / (128.0 * kPi) * (a * a * a);
 }
 
+// Normalised truncated Gaussian of radius k = 3 (Section "Smoothing kernel
+// choice"): w(q) = (e^{-q^2} - e^{-k^2}) / w_G and f(q) = w'(q)/q =
+// -2 e^{-q^2} / w_G for q < k (the derivative's sign, as for the Wendland f).
+__device__ inline double gauss_w(const Grid& g, double q) {
+    if (!(q < kGaussK)) return 0.0;
+    return (exp(-q * q) - g.gauss_tail) / g.gauss_norm;
+}
+
+__device__ inline double gauss_f(const Grid& g, double q) {
+    if (!(q < kGaussK)) return 0.0;
+    return -2.0 * exp(-q * q) / g.gauss_norm;
+}
+
+// The handle's kernel: w(q) and f(q) (W = w/h^3, F = f/h^5).
+__device__ inline double kernel_w(const Grid& g, double q) {
+    return g.kernel == SPH_KERNEL_GAUSSIAN ? gauss_w(g, q) : wendland_w(q);
+}
+__device__ inline double kernel_f(const Grid& g, double q) {
+    return g.kernel == SPH_KERNEL_GAUSSIAN ? gauss_f(g, q) : wendland_f(q);
+}
+
 // Displacement on one axis, minimum image on periodic axes.  Rounded exactly
 // like the neighbour predicate everywhere in the library (contraction off).
 __device__ inline double disp(double xb, double xa, double period) {
@@ -122,7 +143,7 @@ __device__ inline void for_each_neighbor(const NbrView& nv, int32_t row, F&& f) 
 __device__ inline double pair_w_v(const Grid& g, int avg, double mu_a, double mr_a, double mu_b, double ir_b,
                                   double r2) {
     const double q = sqrt(r2) * g.inv_h;
-    const double F = wendland_f(q) * g.inv_h5;
+    const double F = kernel_f(g, q) * g.inv_h5;
     const double tm = two_mubar(mu_a, mu_b, avg);
     return -(tm * mr_a * F) * ir_b;
 }
@@ -135,7 +156,7 @@ __device__ inline double pair_w(const PartView& pv, const Grid& g, int avg, int3
 // Kernel value W_ba of the dummy-wall rows (eq. dummyvel).
 __device__ inline double pair_W(const Grid& g, double r2) {
     const double q = sqrt(r2) * g.inv_h;
-    return wendland_w(q) * g.inv_h3;
+    return kernel_w(g, q) * g.inv_h3;
 }
 
 // ---------------------------------------------------------------------------

@@ -19,6 +19,7 @@ constexpr int kMaxWaves = kMaxBlock / kWave;
 constexpr int kApplyMaxBlock = 256;  // largest block of the operator kernels (register budget)
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kGaussK = 3.0;  // radius of the truncated Gaussian kernel, in units of h
 
 // ---------------------------------------------------------------------------
 // Cell grid of a neighbour handle.  Cells are at least 2h wide on every axis,
@@ -31,8 +32,11 @@ struct Grid {
     double period[3];   // period on periodic axes, 0 elsewhere
     int32_t per[3];     // periodic flags
     double h;           // smoothing length
-    double cut2;        // (2h)^2, the neighbour predicate's bound
+    double cut2;        // (support radius)^2, the neighbour predicate's bound
     double inv_h, inv_h3, inv_h5;  // 1/h, 1/h^3, 1/h^5
+    int32_t kernel;     // SPH_KERNEL_WENDLAND / SPH_KERNEL_GAUSSIAN
+    double gauss_norm;  // w_G of the truncated Gaussian
+    double gauss_tail;  // e^{-k^2}, its value at the cut
 };
 
 // One particle's position in cell order, padded to 32 bytes so that a

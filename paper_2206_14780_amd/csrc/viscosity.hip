@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_papa_visc(NbrView nv, PartView pv, c
         const Pos4 pa = nv.pos[a];
         const double r[3] = {disp(pa.x, pb.x, g.period[0]), disp(pa.y, pb.y, g.period[1]),
                              disp(pa.z, pb.z, g.period[2])};
-        const double F = wendland_f(sqrt(r2) * g.inv_h) * g.inv_h5;
+        const double F = kernel_f(g, sqrt(r2) * g.inv_h) * g.inv_h5;
         const double vf = pv.mu_mr[a].y * F;
         const V3<T> ua = ld3(u, a);
         const double du[3] = {(double)ua.x - (double)ub.x, (double)ua.y - (double)ub.y,

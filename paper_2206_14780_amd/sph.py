@@ -23,6 +23,7 @@ SPH_F64, SPH_F32, SPH_MIXED = 0, 1, 2
 SPH_WALL_DYNAMIC, SPH_WALL_DUMMY = 0, 1
 SPH_AVG_ARITH, SPH_AVG_HARMONIC = 0, 1
 SPH_ROBUST, SPH_STANDARD, SPH_CG = 0, 1, 2
+SPH_KERNEL_WENDLAND, SPH_KERNEL_GAUSSIAN = 0, 1
 SPH_OP_CACHED, SPH_OP_ONTHEFLY = 0, 1
 SPH_CONVERGED, SPH_STATE_STALLED, SPH_PROGRESSING = 0, 1, 2
 SPH_MLP_NPARAM, SPH_MLP_SAMPLE = 8835, 8
@@ -37,7 +38,7 @@ class sph_particles(C.Structure):
 
 class sph_domain(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int32 * 3),
-                ("h", C.c_double)]
+                ("h", C.c_double), ("kernel", C.c_int32)]
 
 
 class sph_visc_params(C.Structure):
@@ -180,11 +181,12 @@ class Particles:
         return s
 
 
-def make_domain(lo, hi, periodic, h) -> sph_domain:
+def make_domain(lo, hi, periodic, h, kernel=SPH_KERNEL_WENDLAND) -> sph_domain:
     d = sph_domain()
     for a in range(3):
         d.lo[a], d.hi[a], d.periodic[a] = float(lo[a]), float(hi[a]), int(periodic[a])
     d.h = float(h)
+    d.kernel = int(kernel)
     return d
 
 

@@ -15,7 +15,7 @@ def to_np(ts):
 
 
 def domain_of(w):
-    return S.make_domain(w.lo, w.hi, w.periodic, w.h)
+    return S.make_domain(w.lo, w.hi, w.periodic, w.h, getattr(w, "kernel", S.SPH_KERNEL_WENDLAND))
 
 
 class GpuCase:
