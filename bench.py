@@ -18,7 +18,8 @@ workload, and the plain-versus-learned comparison: on held-out 160^3 boxes
 1e-6 relative residual of the plain previous-step start with the FP64
 operator against the learned start with the FP32 operator (FP64 solution).
 Also reported: whole steps of the robust BiCGSTAB and of the rotated CG on
-the same tank with dynamic walls (the symmetric case the CG is for).
+the same tank with dynamic walls (the symmetric case the CG is for), and of
+the tank with the Wendland and with the truncated Gaussian kernel.
 """
 import argparse
 import json
@@ -72,6 +73,9 @@ def parse():
     ap.add_argument("--cg-n", type=int, default=100,
                     help="tank side of the CG-versus-BiCGSTAB comparison on dynamic walls (0 = skip)")
     ap.add_argument("--cg-steps", type=int, default=3, help="timed steps per solver in that comparison")
+    ap.add_argument("--kernel-n", type=int, default=100,
+                    help="tank side of the Wendland-versus-Gaussian comparison (0 = skip)")
+    ap.add_argument("--kernel-steps", type=int, default=3, help="timed steps per kernel in that comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device once "
                          "(a kernel of known traffic to scale hardware byte counters)")
@@ -207,6 +211,66 @@ def cg_vs_bicgstab(ctx, n, steps, prec_name):
     return out
 
 
+def kernel_comparison(ctx, n, steps, prec_name):
+    """Whole steps on the benchmark tank with the Wendland kernel (support 2h,
+    ~80 neighbours) and the truncated Gaussian (support 3h, ~250), robust
+    BiCGSTAB, FP32 operator and vectors, to 1e-6."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import workloads as W
+
+    prec = S.SPH_F32 if prec_name == "f32" else S.SPH_F64
+    esz = 4 if prec == S.SPH_F32 else 8
+    out = {"workload": f"open-top tank {n}^3 jittered fluid + 3 wall layers (dummy), nu=10, dt*nu/dp^2=50, "
+                       f"{prec_name} vectors/operator + f64 scalars, cached operator, robust BiCGSTAB to 1e-6; "
+                       f"whole step (neighbours + matrix + solve)"}
+    for name, kern in (("wendland", W.KERNEL_WENDLAND), ("gaussian", W.KERNEL_GAUSSIAN)):
+        w = dataclasses.replace(W.open_box(n=n), kernel=kern)
+        parts = S.device_particles(w)
+        dom = S.make_domain(w.lo, w.hi, w.periodic, w.h, kern)
+        rhs = S.device_vec3(w.rhs, prec)
+        x0 = S.device_vec3(w.x0, prec)
+        x = [t.clone() for t in x0]
+        params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
+        opts = S.make_opts(tol=w.tol, x0_given=True, profile=PROFILE_EVERY)
+
+        def step():
+            for a, b in zip(x, x0):
+                a.copy_(b)
+            nb = ctx.sph_build_neighbors(parts, dom)
+            rep = ctx.sph_visc_solve(nb, None, parts, params, prec, rhs, x, opts)
+            nb.free()
+            assert rep["status"] == S.SPH_OK, (name, rep)
+            return rep
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = reps[-1]
+        a_ms = sum(q["apply_ms"] for q in reps) / max(sum(q["apply_launches"] for q in reps), 1)
+        alg = r["mat_nnz"] * (4 + esz) + w.n * (7 * esz) + ((w.n + 63) // 64) * 8
+        out[name] = {"ms_per_step": round(ms, 3), "iterations": r["iters"],
+                     "setup_ms": round(float(np.median([q["setup_ms"] for q in reps])), 3),
+                     "nnz_per_row": round(r["mat_nnz"] / w.n, 1), "slots_per_row": round(r["mat_slots"] / w.n, 1),
+                     "avg_launch_ms": round(a_ms, 4),
+                     "hbm_frac": round(alg / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if a_ms > 0 else None,
+                     "true_rel_res": round(max(float(np.sqrt(t / b)) for t, b in zip(r["true_rr"], r["bb"]) if b > 0), 9)}
+        print(f"[bench] {name} kernel: {json.dumps(out[name])}", flush=True)
+        del parts, rhs, x0, x
+    out["gaussian_cost_per_launch"] = round(out["gaussian"]["avg_launch_ms"] / out["wendland"]["avg_launch_ms"], 3)
+    out["gaussian_step_ratio"] = round(out["gaussian"]["ms_per_step"] / out["wendland"]["ms_per_step"], 3)
+    out["paper_context"] = ("the paper estimates the Gaussian kernel about 4x as expensive to evaluate, with about "
+                            "twice the neighbour-list memory, partly repaid by fewer iterations")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,6 +359,11 @@ def main():
         print("[bench] CG vs BiCGSTAB (dynamic walls)", flush=True)
         cg = cg_vs_bicgstab(ctx, args.cg_n, args.cg_steps, args.prec)
 
+    kc = None
+    if args.kernel_n > 0:
+        print("[bench] Wendland vs Gaussian kernel", flush=True)
+        kc = kernel_comparison(ctx, args.kernel_n, args.kernel_steps, args.prec)
+
     cpu = None
     if args.cpu_sample_iters > 0:
         print("[bench] cpu baseline (oracle)", flush=True)
@@ -326,6 +395,7 @@ def main():
         "roofline": roofline,
         "plain_vs_learned": pvl,
         "cg_vs_bicgstab": cg,
+        "kernel_comparison": kc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
