@@ -313,24 +313,29 @@ __global__ __launch_bounds__(kBlock) void k_row_fill(NbrView nv, PartView pv, Op
 //   k-th neighbour at different points of the scan, so a direct store of each
 //   index would scatter partial cache lines (several times the list size
 //   written to HBM); each lane instead collects kChunk indices in LDS and
-//   writes them as one 64-byte segment.  List layout: entry k of row r sits
-//   at ((r/64 * kChunks + k/kChunk) * 64 + r%64) * kChunk + k%kChunk.
+//   writes them as one 64-byte segment.  List layout, with cap entries per
+//   row (cap / kChunk segments): entry k of row r sits at
+//   ((r/64 * cap/kChunk + k/kChunk) * 64 + r%64) * kChunk + k%kChunk.
 // k_row_fill_list: one lane per row of a slice, the lanes walking their
 //   lists in step: the pair weights in list order (= scan order) give the
 //   row sum and the FP64 diagonal and are kept, slot-major (entry k of the
 //   64 rows of a slice written together); a second walk scales them into the
-//   slots, which the lanes also write together.  A row with more than
-//   kListCap neighbours keeps no list and is rescanned here.
+//   slots, which the lanes also write together.  A row with more than cap
+//   neighbours keeps no list and is rescanned here.  cap is 96 for the
+//   Wendland kernel (~80 neighbours) and 288 for the truncated Gaussian
+//   (~250), unless the lists of a large system would not fit their budget
+//   (then 96, and its rows are all rescanned).
 // Same pairs, summation order and coefficients as the scan-order build.
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 16;                    // indices per segment
-constexpr int kListCap = 96;                  // listed neighbours per row
-constexpr int kChunks = kListCap / kChunk;
+constexpr int kListCap = 96;                  // listed neighbours per row, Wendland kernel
+constexpr int kListCapGauss = 288;            // the same, truncated Gaussian
+constexpr size_t kListBudget = size_t(24) << 30;  // bytes of lists and weights at most
 constexpr int kBufStride = kChunk + 1;        // LDS words per lane (odd: no bank conflicts)
-static_assert(kListCap % kChunk == 0, "whole segments");
+static_assert(kListCap % kChunk == 0 && kListCapGauss % kChunk == 0, "whole segments");
 
-__device__ inline int64_t list_base(int64_t r) {
-    return ((r / kWave) * kChunks * kWave + (r % kWave)) * kChunk;
+__device__ inline int64_t list_base(int64_t r, int32_t cap) {
+    return ((r / kWave) * (cap / kChunk) * kWave + (r % kWave)) * kChunk;
 }
 __device__ inline int64_t list_off(int32_t k) {
     return (int64_t)(k / kChunk) * (kWave * kChunk) + (k % kChunk);
@@ -346,13 +351,13 @@ __device__ inline int row_kind(const PartView& pv, const OpParams& op, int32_t r
 
 __global__ __launch_bounds__(kBlock) void k_row_scan(NbrView nv, PartView pv, OpParams op,
                                                      int32_t* __restrict__ cnt, int32_t* __restrict__ creal,
-                                                     int32_t* __restrict__ list) {
+                                                     int32_t* __restrict__ list, int32_t cap) {
     __shared__ int32_t buf[kBlock * kBufStride];
     const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (b >= nv.n) return;  // (each lane uses only its own LDS words)
     const int32_t row = (int32_t)b;
     int32_t* my = buf + threadIdx.x * kBufStride;
-    int32_t* out = list + list_base(b);
+    int32_t* out = list + list_base(b, cap);
     const auto flush = [&](int32_t q) {
         int4* dst = reinterpret_cast<int4*>(out + (int64_t)q * (kWave * kChunk));
 #pragma unroll
@@ -363,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_row_scan(NbrView nv, PartView pv, Op
     const auto push = [&](int32_t a) {
         const int32_t e = sc.c % kChunk;
         my[e] = a;
-        if (e == kChunk - 1 && sc.c < kListCap) flush(sc.c / kChunk);
+        if (e == kChunk - 1 && sc.c < cap) flush(sc.c / kChunk);
         sc.add(a);
     };
     const int kind = row_kind(pv, op, row);
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_row_scan(NbrView nv, PartView pv, Op
             if (pv.type[a] == SPH_FLUID) push(a);
         });
     }
-    if (sc.c <= kListCap && sc.c % kChunk) flush(sc.c / kChunk);
+    if (sc.c <= cap && sc.c % kChunk) flush(sc.c / kChunk);
     cnt[row] = sc.slots;
     creal[row] = sc.c;
 }
@@ -387,7 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
                                                           const int64_t* __restrict__ sl_ptr, T* __restrict__ coef,
                                                           uint16_t* __restrict__ dcol, float* __restrict__ lo,
                                                           int32_t* __restrict__ c0, T* __restrict__ dg,
-                                                          double* __restrict__ rs64, double* __restrict__ diag64) {
+                                                          double* __restrict__ rs64, double* __restrict__ diag64,
+                                                          int32_t cap) {
     const int64_t r = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (r >= nslices * kWave) return;
     const Grid& g = nv.g;
@@ -396,9 +402,9 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
     const int32_t row = valid ? (int32_t)r : 0;
     const int kind = valid ? row_kind(pv, op, row) : kRowNone;
     int32_t c = kind != kRowNone ? creal[row] : 0;
-    const bool listed = c <= kListCap;
-    const int32_t* lst = list + list_base(r);
-    double* wl = wlist + (r / kWave) * (kListCap * kWave) + r % kWave;  // entry k at wl[k * kWave]
+    const bool listed = c <= cap;
+    const int32_t* lst = list + list_base(r, cap);
+    double* wl = wlist + (r / kWave) * ((int64_t)cap * kWave) + r % kWave;  // entry k at wl[k * kWave]
     const Pos4 pb = nv.pos[row];
     const double mu_b = pv.mu[row], ir_b = pv.inv_rho[row];
     const auto weight = [&](int32_t a, double r2) {
@@ -487,6 +493,12 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     // SPH_BUILD_LEGACY=1 selects the build with the coefficients evaluated
     // inside the scan (the reference the list build is tested against)
     const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
+    // list entries per row: room for every neighbour of the kernel's support
+    // (int32 index + FP64 weight each) while that fits the budget
+    const int32_t cap = nb->g.kernel == SPH_KERNEL_GAUSSIAN &&
+                                (size_t)nslices * kWave * kListCapGauss * 12 <= kListBudget
+                            ? kListCapGauss
+                            : kListCap;
     int32_t *cnt = nullptr, *creal = nullptr, *list = nullptr;
     double *d = nullptr, *ws = nullptr, *wlist = nullptr;
     int64_t *size = nullptr, *ptr = nullptr;
@@ -506,10 +518,10 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
         hipLaunchKernelGGL(k_row_count, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream,
                            nb->view(), pv, op, cnt, creal, d, ws);
     } else {
-        SPH_TRY(ctx->ensure_t(kList, (size_t)nslices * kListCap * kWave, &list));
-        SPH_TRY(ctx->ensure_t(kWList, (size_t)nslices * kListCap * kWave, &wlist));
+        SPH_TRY(ctx->ensure_t(kList, (size_t)nslices * cap * kWave, &list));
+        SPH_TRY(ctx->ensure_t(kWList, (size_t)nslices * cap * kWave, &wlist));
         hipLaunchKernelGGL(k_row_scan, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal,
-                           list);
+                           list, cap);
     }
     hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
                        n, nslices, (int32_t)pack_of<T>(), cnt, creal, size, nnz_dev);
@@ -542,7 +554,7 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
         // did not): 8.1 -> 5.8 ms at 4.49M particles.
         constexpr size_t kFillLdsReserve = 60 * 1024;
         hipLaunchKernelGGL(k_row_fill_list<T>, slice_grid, dim3(kBlock), kFillLdsReserve, ctx->stream, nb->view(), pv, op,
-                           nslices, creal, list, wlist, ptr, coef, dcol, lo, c0, dg, rs64, d);
+                           nslices, creal, list, wlist, ptr, coef, dcol, lo, c0, dg, rs64, d, cap);
         SPH_LAUNCHED("k_row_fill_list");
     } else {
         hipLaunchKernelGGL(k_row_fill<T>, dim3((unsigned)ceil_div(nslices * kWave, kBlock)), dim3(kBlock), 0,

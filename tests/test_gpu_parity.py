@@ -282,10 +282,15 @@ def test_list_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, mon
     # bit: same pairs, same summation order, same coefficients and row sums.
     # The channels have periodic axes of 1 and 2 cells; in the wide-kernel
     # tank (h = 1.5 dp, ~113 neighbours) most rows exceed the 96-entry list
-    # and are rescanned by the fill.
+    # and are rescanned by the fill.  With the truncated Gaussian (~250
+    # neighbours) the lists hold 288 entries: the tank's rows are listed, the
+    # Gaussian wide tank (h = 1.5 dp, ~380) is rescanned again.
     wide = dataclasses.replace(small_tank(seed=65, n=(10, 10, 6), wall=wall), h=1.5)
+    gauss = dataclasses.replace(W.open_box(12, wall=wall), kernel=W.KERNEL_GAUSSIAN)
+    gwide = dataclasses.replace(wide, kernel=W.KERNEL_GAUSSIAN)
     cases = (small_tank(seed=61, wall=wall), W.open_box(14, wall=wall),
-             W.poiseuille(4, wall=wall, shuffle_seed=63), W.poiseuille(6, wall=wall, shuffle_seed=64), wide)
+             W.poiseuille(4, wall=wall, shuffle_seed=63), W.poiseuille(6, wall=wall, shuffle_seed=64), wide,
+             gauss, gwide)
     for w in cases:
         print(f"[build] {w.name} h={w.h} prec={prec} jacobi={jacobi}", flush=True)
         g = GpuCase(ctx, w)
@@ -301,6 +306,10 @@ def test_list_matrix_build_matches_scan_order_build(ctx, prec, wall, jacobi, mon
         assert rs["history"] == rl["history"] and np.array_equal(Xs, Xl)
         if w is wide:
             assert rs["mat_nnz"] > 96 * (w.ptype == W.FLUID).sum()  # every fluid row has 98+
+        if w is gauss:
+            assert 150 * (w.ptype == W.FLUID).sum() < rs["mat_nnz"] < 288 * w.n
+        if w is gwide:
+            assert rs["mat_nnz"] > 288 * (w.ptype == W.FLUID).sum()
 
 
 def _wide_slab():
