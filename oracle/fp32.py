@@ -1,0 +1,112 @@
+"""Single-precision BiCGSTAB (TEST INFRASTRUCTURE ONLY: used by the test
+suite; the product path never imports it).
+
+The paper's all-FP32 solver (Section "Restructuring the stabilized
+biconjugate gradient method", appendix "Implementation notes"): vectors,
+operator results and every scalar in FP32, inner products compensated.  Plain
+numpy float32 arrays; each inner product is the FP64 sum of the FP32 products
+rounded once to FP32 (a compensated FP32 sum is within about a unit of that
+value's last place); the operator is the oracle's FP64 operator applied to the
+FP32 vector and rounded once to FP32 (coefficients evaluated in FP64, as in
+the library).  Robust and textbook variants, three systems sharing the matrix,
+the three-state stopping rule and tau^2 = max(eps^2 b.b, FLT_MIN), as
+`orc_bicgstab`, without true-residual restarts (the paper's iteration).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import CONVERGED, PROGRESSING, ROBUST, STALLED, Operator
+
+F32 = np.float32
+FLT_MIN = F32(np.finfo(np.float32).tiny)
+
+
+def _dot(a, b):
+    """Per-component inner products (3,) of (n, 3) FP32 arrays."""
+    return (a.astype(np.float64) * b.astype(np.float64)).sum(axis=0).astype(F32)
+
+
+def _div(a, b):
+    """Componentwise a / b in FP32, 0 where b is 0 or the quotient is not finite."""
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        q = np.where(b != 0, a / np.where(b != 0, b, F32(1)), F32(0)).astype(F32)
+    return np.where(np.isfinite(q), q, F32(0)).astype(F32)
+
+
+def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_stall=None):
+    """A V = B (three columns) in single precision.  Returns (X (n, 3) FP32,
+    report dict with iters, state, stall_count, rr, tau2, and history
+    (iters + 1, 3) of r.r)."""
+    def A(v):
+        return op.apply(v.astype(np.float64)).astype(F32)
+
+    b = np.asarray(B, dtype=np.float64)
+    if op.jacobi:
+        b = b / op.diag()[:, None]
+    b = b.astype(F32)
+    x = np.zeros_like(b)
+    r = b.copy()
+    rh = r.copy()
+    bb = _dot(b, b)
+    tau2 = np.maximum((F32(tol) * F32(tol)) * bb, FLT_MIN).astype(F32)
+    rr = _dot(r, r)
+    gam = _dot(rh, r)
+    p = np.zeros_like(b)
+    Ap = np.zeros_like(b)
+    alphap = np.zeros(3, F32)
+    beta = np.zeros(3, F32)
+    gprev = np.ones(3, F32)
+    alpha = np.ones(3, F32)
+    omega = np.ones(3, F32)
+    state = np.where(rr < tau2, CONVERGED, PROGRESSING)
+    stalls = np.zeros(3, np.int64)
+    hist = [rr.copy()]
+    it = 0
+    fi, fc = force_stall if force_stall is not None else (-1, -1)
+    while np.any(state == PROGRESSING) and it < max_iter:
+        it += 1
+        stall = np.zeros(3, bool)
+        if variant == ROBUST:
+            # p = (r + beta p) - alpha' A p, each operation rounded to FP32
+            p = ((r + beta * p) - alphap * Ap).astype(F32)
+        else:
+            g = _dot(rh, r)
+            bt = (_div(g, gprev) * _div(alpha, omega)).astype(F32)
+            bt = np.where((gprev != 0) & (omega != 0), bt, F32(0)).astype(F32)
+            stall |= g == 0
+            gam = g
+            beta = bt
+            p = (r + bt * (p - omega * Ap)).astype(F32)
+        Ap = A(p)
+        delta = _dot(rh, Ap)
+        if it == fi:
+            delta[fc] = F32(0)
+        alpha = _div(gam, delta)
+        stall |= (alpha == 0) | (delta == 0)
+        s = (r - alpha * Ap).astype(F32)
+        As = A(s)
+        tt = _dot(As, As)
+        ts = _dot(As, s)
+        w = _div(ts, tt)
+        stall |= w == 0
+        if variant != ROBUST:
+            w = np.where(_dot(s, s) < tau2, F32(0), w).astype(F32)
+        omega = w
+        x = (x + alpha * p + w * s).astype(F32)
+        r = (s - w * As).astype(F32)
+        if variant == ROBUST:
+            g = _dot(rh, r)
+            ap = np.where(stall, F32(0), _div(g, delta)).astype(F32)
+            bt = np.where(stall, F32(0), _div(ap, omega)).astype(F32)
+            stall |= g == 0
+            gam, alphap, beta = g, ap, bt
+        else:
+            gprev = gam
+        rr = _dot(r, r)
+        stalls += stall
+        state = np.where(rr < tau2, CONVERGED, np.where(stall, STALLED, PROGRESSING))
+        hist.append(rr.copy())
+    rep = dict(iters=it, state=[int(v) for v in state], stall_count=[int(v) for v in stalls],
+               rr=[float(v) for v in rr], tau2=[float(v) for v in tau2], bb=[float(v) for v in bb])
+    return x, rep, np.array(hist)
