@@ -161,6 +161,13 @@ typedef struct {
  *          whichever of the learned guess and the plain start (x on entry if
  *          x0_given, else zero) has the smaller FP64 true residual.  The
  *          tolerance and stopping test are unchanged.
+ *   fp32_scalars: 1 = the paper's all-single-precision solver (appendix
+ *          "Implementation notes"; SPH_F32 only, else SPH_E_ARG): every
+ *          reduced inner product and every scalar of the recurrences (alpha,
+ *          beta, omega, gamma, delta, tau^2) is rounded to FP32, the reduced
+ *          sums standing for compensated (Kahan) FP32 sums; the vectors and
+ *          the operator are FP32 as in SPH_F32.  Set true_res_period = 0 and
+ *          restart_drop = 0 for the paper's unrestarted iteration.
  *   warm_u: device, n values of the caller's precision each: u.  A null
  *          component takes the initial guess (x0_given; the usual case of a
  *          previous-step start, which also saves one operator pass) or rhs. */
@@ -178,6 +185,7 @@ typedef struct {
     double restart_drop;
     const float *warm_params;
     const void *warm_u[3];
+    int32_t fp32_scalars;
 } sph_solve_opts;
 
 /* Solve report (host memory).  history, if non-null, is a host buffer of

@@ -30,6 +30,20 @@ namespace sph {
 
 constexpr int kKp = 9;  // partials per block of the close-out / initial-residual kernels
 
+// Single-precision scalars (the paper's all-FP32 solver, appendix
+// "Implementation notes"): with sc.fp32 every reduced inner product and every
+// scalar of the recurrences is rounded to FP32.  The operands being FP32
+// values, an operation evaluated in FP64 and rounded once equals the FP32
+// operation (FP64 has more than 2 x 24 + 2 significand bits); a reduced sum
+// rounded once stands for the compensated FP32 sum, which is within about a
+// unit of its last place.
+__device__ inline double rsc(const SolveConst& sc, double v) { return sc.fp32 ? (double)(float)v : v; }
+template <int K>
+__device__ inline void rsc_all(const SolveConst& sc, double (&v)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = rsc(sc, v[k]);
+}
+
 // Initial residual: r = b - A x0 given in `r0` (null: x0 = 0, r = b),
 // r0hat = r; partials of r0hat . r, r . r and b . b.
 template <typename T>
@@ -85,7 +99,7 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
         double ap = 0.0, bt = 0.0;
         if (it == 1) {
             bb = red[6 + c];
-            tau2 = sc.tol2 * bb;
+            tau2 = rsc(sc, sc.tol2 * bb);
             if (tau2 < sc.floor_) tau2 = sc.floor_;
             if (!finite_d(bb)) o.nonfinite = 1;
         } else {
@@ -95,9 +109,9 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
             if (sc.variant == SPH_ROBUST) {
                 // alpha'_j = gamma_{j+1}/delta_j, beta_j = alpha'_j/omega_j
                 if (!stall) {
-                    ap = g / ctl->delta[prev][c];
+                    ap = rsc(sc, g / ctl->delta[prev][c]);
                     if (!finite_d(ap)) ap = 0.0;
-                    bt = ap / ctl->omega[prev][c];
+                    bt = rsc(sc, ap / ctl->omega[prev][c]);
                     if (!finite_d(bt)) bt = 0.0;
                 }
                 if (g == 0.0) stall = 1;
@@ -107,13 +121,13 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
                 // 0 after a stalled iteration
                 if (!stall) {
                     const double rp = ctl->gam[prev][c];
-                    if (rp != 0.0) bt = g / rp;
+                    if (rp != 0.0) bt = rsc(sc, g / rp);
                     if (!finite_d(bt)) bt = 0.0;
                 }
             } else {
                 // beta_{j+1} = (gamma_{j+1}/gamma_j)(alpha_j/omega_j)
                 const double gp = ctl->gam[prev][c], al = ctl->alpha[prev][c], om = ctl->omega[prev][c];
-                if (gp != 0.0 && om != 0.0) bt = (g / gp) * (al / om);
+                if (gp != 0.0 && om != 0.0) bt = rsc(sc, rsc(sc, g / gp) * rsc(sc, al / om));
                 if (!finite_d(bt)) bt = 0.0;
             }
         }
@@ -189,13 +203,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
     __shared__ double lds[kKp * kMaxWaves];
     double red[kKp];
     reduce_partials<kKp>(part, nblk, red, lds);
+    rsc_all(sc, red);
     const int32_t j = it - 1;
     // periodic FP64 true residual of iteration j, unless a host-issued check
     // already covered it
     const bool check = sc.true_res_period > 0 && j > 0 && j % sc.true_res_period == 0 &&
                        ctl->host_checked_iter != j;
     double tr[3] = {0.0, 0.0, 0.0};
-    if (check) reduce_partials<3>(part_tr, sc.tr_blocks, tr, lds);
+    if (check) {
+        reduce_partials<3>(part_tr, sc.tr_blocks, tr, lds);
+        rsc_all(sc, tr);
+    }
     PScalars s;
     p_scalars(ctl, it, sc, red, tr, check, s);
     const int cur = it & 1;
@@ -290,6 +308,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32
     __shared__ double lds[3 * kMaxWaves];
     double red[3];
     reduce_partials<3>(part, nblk, red, lds);
+    rsc_all(sc, red);
     const int cur = it & 1;
     double al[3];
     int32_t stall[3];
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32
         red[c] = d;
         stall[c] = ctl->stall0[cur][c];
         double a = 0.0;
-        if (d != 0.0 && finite_d(d)) a = ctl->gam[cur][c] / d;
+        if (d != 0.0 && finite_d(d)) a = rsc(sc, ctl->gam[cur][c] / d);
         if (!finite_d(a) || d == 0.0 || !finite_d(d)) {
             a = 0.0;
             stall[c] = 1;
@@ -338,13 +357,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
     __shared__ double lds[kKp * kMaxWaves];
     double red[KA];
     reduce_partials<KA>(part, nblk, red, lds);
+    rsc_all(sc, red);
     const int cur = it & 1;
     double om[3], al[3];
     int32_t stall[3];
     for (int c = 0; c < 3; ++c) {
         const double ts = red[c], tt = red[3 + c];
         double w = 0.0;
-        if (tt != 0.0) w = ts / tt;
+        if (tt != 0.0) w = rsc(sc, ts / tt);
         if (!finite_d(w)) w = 0.0;
         stall[c] = ctl->stallA[cur][c] | (w == 0.0 ? 1 : 0);
         if constexpr (KA == 9) {
@@ -411,6 +431,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, i
     double rho[3], pap[3];
     reduce_partials<3>(part_rho, nrho, rho, lds);
     reduce_partials<3>(part_pap, npap, pap, lds);
+    rsc_all(sc, rho);
+    rsc_all(sc, pap);
     const int cur = it & 1;
     double al[3];
     int32_t stall[3];
@@ -419,7 +441,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, i
         if (it == sc.force_stall_iter && c == sc.force_stall_comp) d = 0.0;
         pap[c] = d;
         double a = 0.0;
-        if (d != 0.0 && finite_d(d)) a = rho[c] / d;
+        if (d != 0.0 && finite_d(d)) a = rsc(sc, rho[c] / d);
         stall[c] = 0;
         if (!finite_d(a) || a == 0.0) {
             a = 0.0;
@@ -479,10 +501,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_walls(int64_t n, const uint8_t* _
 // Host-issued residual check, step 2 (one block): decide which converged
 // components failed the FP64 true residual and must restart.
 __global__ __launch_bounds__(kMaxBlock) void k_check_decide(Ctl* __restrict__ ctl, const double* __restrict__ part,
-                                                            int32_t nblk) {
+                                                            int32_t nblk, SolveConst sc) {
     __shared__ double lds[3 * kMaxWaves];
     double red[3];
     reduce_partials<3>(part, nblk, red, lds);
+    rsc_all(sc, red);
     if (threadIdx.x != 0) return;
     const int32_t j = ctl->iter;
     ctl->n_true_checks += 1;
@@ -539,10 +562,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_check_copy(const Ctl* __restrict_
 }
 
 __global__ __launch_bounds__(kMaxBlock) void k_check_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
-                                                            int32_t nblk) {
+                                                            int32_t nblk, SolveConst sc) {
     __shared__ double lds[6 * kMaxWaves];
     double red[6];
     reduce_partials<6>(part, nblk, red, lds);
+    rsc_all(sc, red);
     if (threadIdx.x != 0) return;
     for (int c = 0; c < 3; ++c) {
         ctl->gam_restart[c] = red[c];
@@ -726,11 +750,11 @@ struct Solver {
 
     void host_check() {
         true_residual(nullptr, pchk);
-        hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl, pchk, L.grid_apply);
+        hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl, pchk, L.grid_apply, sc);
         hipLaunchKernelGGL(k_check_copy<T>, gs(), bs(), 0, ctx->stream, ctl, L.n, tmp, r, rh0,
                            pchk + 3 * (size_t)L.grid_apply);
         hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl,
-                           pchk + 3 * (size_t)L.grid_apply, L.grid_stream);
+                           pchk + 3 * (size_t)L.grid_apply, L.grid_stream, sc);
         launches += 3;
     }
 };
@@ -783,7 +807,13 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     SPH_TRY(ctx->ensure_t(kHist, (size_t)hist_rows * 3, &S.hist));
     SPH_TRY(ctx->ensure_t(kStallHist, (size_t)hist_rows * 3, &S.stallhist));
 
-    S.sc.tol2 = o->tol * o->tol;
+    S.sc.fp32 = o->fp32_scalars ? 1 : 0;
+    if (S.sc.fp32) {
+        const float tf = (float)o->tol;
+        S.sc.tol2 = (double)(tf * tf);
+    } else {
+        S.sc.tol2 = o->tol * o->tol;
+    }
     const bool vec32 = sizeof(T) == 4;
     const bool cg = o->variant == SPH_CG;
     // the drop restart renews the BiCGSTAB's shadow vector; the CG has none
@@ -1020,6 +1050,8 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
         return ctx->fail(SPH_E_ARG, "visc_solve: tol or max_iter out of range");
     if (opts->variant != SPH_ROBUST && opts->variant != SPH_STANDARD && opts->variant != SPH_CG)
         return ctx->fail(SPH_E_ARG, "visc_solve: variant");
+    if (opts->fp32_scalars && prec != SPH_F32)
+        return ctx->fail(SPH_E_ARG, "visc_solve: fp32_scalars needs prec = SPH_F32");
     if (opts->variant == SPH_CG && params && params->wall == SPH_WALL_DUMMY)
         return ctx->fail(SPH_E_ARG, "visc_solve: the CG needs a symmetric system (dynamic walls)");
     if (opts->true_res_period < 0) return ctx->fail(SPH_E_ARG, "visc_solve: true_res_period < 0");

@@ -176,6 +176,7 @@ struct SolveConst {
     int32_t force_stall_iter;
     int32_t force_stall_comp;
     int32_t hist_cap;      // rows of the device history arrays
+    int32_t fp32;          // 1: every reduced inner product and every scalar rounded to FP32
 };
 
 // Launch geometry of the row kernels.

@@ -51,7 +51,8 @@ class sph_solve_opts(C.Structure):
                 ("floor", C.c_double), ("true_res_period", C.c_int32), ("x0_given", C.c_int32),
                 ("poll_every", C.c_int32), ("force_stall_iter", C.c_int32),
                 ("force_stall_comp", C.c_int32), ("profile", C.c_int32),
-                ("restart_drop", C.c_double), ("warm_params", _vp), ("warm_u", _vp * 3)]
+                ("restart_drop", C.c_double), ("warm_params", _vp), ("warm_u", _vp * 3),
+                ("fp32_scalars", C.c_int32)]
 
 
 class sph_step_params(C.Structure):
@@ -196,13 +197,14 @@ def make_params(dt, wall, avg, jacobi=True, op_mode=SPH_OP_CACHED) -> sph_visc_p
 
 def make_opts(tol=1e-8, max_iter=10000, variant=SPH_ROBUST, floor=-1.0, true_res_period=20,
               x0_given=False, poll_every=0, force_stall=None, profile=False,
-              restart_drop=-1.0, warm_params=None, warm_u=None) -> sph_solve_opts:
+              restart_drop=-1.0, warm_params=None, warm_u=None, fp32_scalars=False) -> sph_solve_opts:
     """Solver options; warm_params / warm_u are cuda tensors (kept alive by
     the caller for the duration of the solve)."""
     fi, fc = force_stall if force_stall is not None else (-1, -1)
     o = sph_solve_opts(float(tol), int(max_iter), int(variant), float(floor),
                        int(true_res_period), int(bool(x0_given)), int(poll_every), int(fi), int(fc),
                        int(profile), float(restart_drop))
+    o.fp32_scalars = int(bool(fp32_scalars))
     if warm_params is not None:
         o.warm_params = _ptr(warm_params)
         if warm_u is not None:
