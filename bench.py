@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--kernel-n", type=int, default=100,
                     help="tank side of the Wendland-versus-Gaussian comparison (0 = skip)")
     ap.add_argument("--kernel-steps", type=int, default=3, help="timed steps per kernel in that comparison")
+    ap.add_argument("--fp32-n", type=int, default=100,
+                    help="tank side of the all-FP32 solver study (0 skips it)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device once "
                          "(a kernel of known traffic to scale hardware byte counters)")
@@ -271,6 +273,52 @@ def kernel_comparison(ctx, n, steps, prec_name):
     return out
 
 
+def fp32_paper_study(ctx, n):
+    """The paper's all-FP32 solver (FP32 scalars, no residual restarts) on
+    the benchmark tank from the previous-step start and on a 64^3 plane
+    channel from rest: iterations, solve time and stalls of the robust and
+    textbook variants at 1e-6 and at the FP32 epsilon 2^-23, beside the
+    library's default (FP64 scalars, periodic true-residual restarts)."""
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import workloads as W
+
+    paper = dict(fp32_scalars=True, true_res_period=0, restart_drop=0.0)
+    runs = [("default_f64_scalars", S.SPH_ROBUST, {}),
+            ("paper_robust", S.SPH_ROBUST, paper), ("paper_standard", S.SPH_STANDARD, paper)]
+    out = {"workload": f"open-top tank {n}^3 (dummy walls) from the previous-step start; plane channel 64^3 "
+                       f"(dummy walls) from rest; FP32 vectors and operator, cached operator, max 3000 iterations",
+           "stall_note": "stalls counted on components with a nonzero right-hand side"}
+    for wname, w, use_x0 in (("tank", W.open_box(n=n), True), ("channel64", W.poiseuille(64, wall=W.WALL_DUMMY), False)):
+        parts = S.device_particles(w)
+        dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
+        nb = ctx.sph_build_neighbors(parts, dom)
+        rhs = S.device_vec3(w.rhs, S.SPH_F32)
+        start = w.x0 if use_x0 else np.zeros((w.n, 3))
+        x0 = S.device_vec3(start, S.SPH_F32)
+        live = [c for c in range(3) if np.any(w.rhs[:, c] != 0)]
+        params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
+        res = {}
+        for tol_name, tol in (("tol_1e-6", 1e-6), ("tol_2^-23", 2.0 ** -23)):
+            for name, var, extra in runs:
+                x = [t.clone() for t in x0]
+                o = S.make_opts(tol=tol, x0_given=use_x0, max_iter=3000, variant=var, **extra)
+                rep = ctx.sph_visc_solve(nb, None, parts, params, S.SPH_F32, rhs, x, o)
+                torch.cuda.synchronize()
+                res[f"{tol_name}/{name}"] = {
+                    "status": rep["status"], "iterations": rep["iters"],
+                    "solve_ms": round(rep["setup_ms"] + rep["iterate_ms"], 3),
+                    "stalls": [rep["stall_count"][c] for c in live],
+                    "true_rel_res": [round(float(np.sqrt(rep["true_rr"][c] / rep["bb"][c])), 10) for c in live]}
+        nb.free()
+        out[wname] = res
+        print(f"[bench] fp32 study {wname}: {json.dumps(res)}", flush=True)
+        del parts, rhs, x0
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -364,6 +412,11 @@ def main():
         print("[bench] Wendland vs Gaussian kernel", flush=True)
         kc = kernel_comparison(ctx, args.kernel_n, args.kernel_steps, args.prec)
 
+    f32s = None
+    if args.fp32_n > 0:
+        print("[bench] all-FP32 solver study", flush=True)
+        f32s = fp32_paper_study(ctx, args.fp32_n)
+
     cpu = None
     if args.cpu_sample_iters > 0:
         print("[bench] cpu baseline (oracle)", flush=True)
@@ -396,6 +449,7 @@ def main():
         "plain_vs_learned": pvl,
         "cg_vs_bicgstab": cg,
         "kernel_comparison": kc,
+        "fp32_paper": f32s,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -195,7 +195,9 @@ typedef struct {
     int32_t iters;
     int32_t status;
     int32_t state[3];       /* SPH_CONVERGED / SPH_STATE_STALLED / SPH_PROGRESSING */
-    int32_t stall_count[3]; /* iterations in which the component broke down */
+    int32_t stall_count[3]; /* iterations in which the component broke down (a
+                               component with a zero right-hand side, converged at
+                               the start, breaks down in every iteration) */
     double rr[3];           /* final recursive r.r of the scaled system */
     double bb[3];           /* b.b of the scaled right-hand side */
     double tau2[3];
