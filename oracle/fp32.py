@@ -10,16 +10,21 @@ value's last place); the operator is the oracle's FP64 operator applied to the
 FP32 vector and rounded once to FP32 (coefficients evaluated in FP64, as in
 the library).  Robust and textbook variants, three systems sharing the matrix,
 the three-state stopping rule and tau^2 = max(eps^2 b.b, FLT_MIN), as
-`orc_bicgstab`, without true-residual restarts (the paper's iteration).
+`orc_bicgstab`, without true-residual restarts (the paper's iteration).  The
+rotated CG (Section "Restructuring the Conjugate Gradient") likewise, as
+`orc_cg`: Jacobi-weighted products <u, v>_D = sum D_i u_i v_i (the FP64
+diagonal times the FP32 products, summed in FP64, rounded once), wall rows
+started at their exact value.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import CONVERGED, PROGRESSING, ROBUST, STALLED, Operator
+from . import CONVERGED, FLUID_TYPE, PROGRESSING, ROBUST, STALLED, Operator
 
 F32 = np.float32
 FLT_MIN = F32(np.finfo(np.float32).tiny)
+WALL_DYNAMIC = 0
 
 
 def _dot(a, b):
@@ -34,6 +39,18 @@ def _div(a, b):
     return np.where(np.isfinite(q), q, F32(0)).astype(F32)
 
 
+def _dot_w(D, a, b):
+    """Per-component <a, b>_D (D None: Euclidean), FP64 sum rounded once."""
+    if D is None:
+        return _dot(a, b)
+    return (D[:, None] * a.astype(np.float64) * b.astype(np.float64)).sum(axis=0).astype(F32)
+
+
+def _rhs(op: Operator, B):
+    b = np.asarray(B, dtype=np.float64)
+    return b / op.diag()[:, None] if op.jacobi else b
+
+
 def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_stall=None):
     """A V = B (three columns) in single precision.  Returns (X (n, 3) FP32,
     report dict with iters, state, stall_count, rr, tau2, and history
@@ -41,10 +58,7 @@ def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_
     def A(v):
         return op.apply(v.astype(np.float64)).astype(F32)
 
-    b = np.asarray(B, dtype=np.float64)
-    if op.jacobi:
-        b = b / op.diag()[:, None]
-    b = b.astype(F32)
+    b = _rhs(op, B).astype(F32)
     x = np.zeros_like(b)
     r = b.copy()
     rh = r.copy()
@@ -103,6 +117,57 @@ def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_
             gam, alphap, beta = g, ap, bt
         else:
             gprev = gam
+        rr = _dot(r, r)
+        stalls += stall
+        state = np.where(rr < tau2, CONVERGED, np.where(stall, STALLED, PROGRESSING))
+        hist.append(rr.copy())
+    rep = dict(iters=it, state=[int(v) for v in state], stall_count=[int(v) for v in stalls],
+               rr=[float(v) for v in rr], tau2=[float(v) for v in tau2], bb=[float(v) for v in bb])
+    return x, rep, np.array(hist)
+
+
+def cg_solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, force_stall=None):
+    """Rotated CG for the symmetric case (dynamic walls) in single precision.
+    Returns (X (n, 3) FP32, report dict as `solve`, history of r.r)."""
+    if op.wall != WALL_DYNAMIC:
+        raise ValueError("CG needs a symmetric system: dynamic walls")
+
+    def A(v):
+        return op.apply(v.astype(np.float64)).astype(F32)
+
+    b64 = _rhs(op, B)
+    b = b64.astype(F32)
+    D = op.diag() if op.jacobi else None
+    x = np.zeros_like(b)
+    walls = op._type != FLUID_TYPE
+    x[walls] = b[walls]
+    # the starting residual in FP64 from the FP32 start, rounded once
+    r = (b64 - op.apply(x.astype(np.float64))).astype(F32)
+    bb = _dot(b, b)
+    tau2 = np.maximum((F32(tol) * F32(tol)) * bb, FLT_MIN).astype(F32)
+    rr = _dot(r, r)
+    rho = _dot_w(D, r, r)
+    beta = np.zeros(3, F32)
+    p = np.zeros_like(b)
+    state = np.where(rr < tau2, CONVERGED, PROGRESSING)
+    stalls = np.zeros(3, np.int64)
+    hist = [rr.copy()]
+    it = 0
+    fi, fc = force_stall if force_stall is not None else (-1, -1)
+    while np.any(state == PROGRESSING) and it < max_iter:
+        it += 1
+        p = (r + beta * p).astype(F32)
+        Ap = A(p)
+        pap = _dot_w(D, p, Ap)
+        if it == fi:
+            pap[fc] = F32(0)
+        alpha = _div(rho, pap)
+        stall = alpha == 0
+        x = (x + alpha * p).astype(F32)
+        r = (r - alpha * Ap).astype(F32)
+        rho_new = _dot_w(D, r, r)
+        beta = np.where(stall, F32(0), _div(rho_new, rho)).astype(F32)
+        rho = rho_new
         rr = _dot(r, r)
         stalls += stall
         state = np.where(rr < tau2, CONVERGED, np.where(stall, STALLED, PROGRESSING))

@@ -8,6 +8,7 @@ import pytest
 
 import oracle as O
 from oracle import fp32 as OF
+from paper_2206_14780_amd import workloads as W
 
 from test_oracle_operator import _tank
 
@@ -60,3 +61,50 @@ def test_forced_stall_stays_in_its_component():
     assert r1["stall_count"][0] == 0 and r1["stall_count"][2] == 0
     n = min(len(h0), len(h1))
     assert np.array_equal(h0[:n, 0], h1[:n, 0]) and np.array_equal(h0[:n, 2], h1[:n, 2])
+
+
+# --- rotated CG in single precision (symmetric case: dynamic walls, uniform mass)
+
+def _sym_case(seed=7, jacobi=True):
+    from test_oracle_cg import _rhs, _sym_tank
+    kw, pt = _sym_tank(seed=seed)
+    return O.Operator(jacobi=jacobi, **kw), _rhs(pt, seed), pt
+
+
+@pytest.mark.parametrize("jacobi", [True, False])
+def test_fp32_cg_solution_and_types(jacobi):
+    op, B, pt = _sym_case(jacobi=jacobi)
+    X, rep, h = OF.cg_solve(op, B, tol=1e-6)
+    assert X.dtype == np.float32 and h.dtype == np.float32
+    assert rep["state"] == [O.CONVERGED] * 3
+    assert all(np.float32(v) == v for v in rep["rr"] + rep["tau2"])
+    b = B / op.diag()[:, None] if jacobi else B
+    wr = pt != W.FLUID
+    # wall rows start at their value rounded to FP32; the FP64 starting
+    # residual keeps only that rounding, so they move by at most about it
+    assert np.all(np.abs(X[wr] - b[wr]) <= 2.0 ** -22 * np.abs(b[wr]))
+    Xd = O.dense_solve(op, B)
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 2e-5
+
+
+@pytest.mark.parametrize("jacobi", [True, False])
+def test_fp32_cg_first_iterates_follow_fp64(jacobi):
+    op, B, _ = _sym_case(seed=3, jacobi=jacobi)
+    _, r32, h32 = OF.cg_solve(op, B, tol=0.0, max_iter=4)
+    _, r64, h64 = O.cg_solve(op, B, tol=1e-30, max_iter=4, true_res_period=0)
+    assert r32["iters"] == r64["iters"] == 4
+    d = np.abs(h32 / h64 - 1.0).max(axis=1)
+    assert d[0] < 1e-6 and np.all(d < 1e-4)
+
+
+def test_fp32_cg_forced_stall_and_dummy_walls_refused():
+    op, B, _ = _sym_case(seed=9)
+    _, r0, h0 = OF.cg_solve(op, B, tol=1e-6)
+    _, r1, h1 = OF.cg_solve(op, B, tol=1e-6, force_stall=(2, 1))
+    assert r0["stall_count"] == [0, 0, 0] and r1["stall_count"] == [0, 1, 0]
+    assert r1["state"] == [O.CONVERGED] * 3
+    n = min(len(h0), len(h1))
+    assert np.array_equal(h0[:n, 0], h1[:n, 0]) and np.array_equal(h0[:n, 2], h1[:n, 2])
+    kw, _ = _tank(wall=W.WALL_DUMMY)
+    with pytest.raises(ValueError):
+        OF.cg_solve(O.Operator(jacobi=True, **kw), B)
