@@ -101,3 +101,29 @@ def test_fp32_scalars_tank_100(ctx):
         assert r["status"] == 0 and max(rel) <= w.tol * (1 + 1e-6)
     assert rr["stall_count"] == [0, 0, 0]
     assert max(e[0], e[1]) <= 2.0 * e[2] + 1e-6
+
+
+@pytest.mark.parametrize("jacobi", [True, False])
+def test_fp32_scalars_cg_parity(ctx, jacobi):
+    # the rotated CG in the all-FP32 form against the FP32 oracle's CG, on a
+    # symmetric tank (dynamic walls, uniform mass) with moving walls
+    import dataclasses
+    w = small_tank(seed=37, wall=W.WALL_DYNAMIC, mu_span=100.0, dt_nu=10.0)
+    w = dataclasses.replace(w, mass=np.full(w.n, 1.0))
+    B = w.rhs.copy()
+    wr = w.ptype != W.FLUID
+    B[wr] = np.random.default_rng(37).normal(scale=0.1, size=(int(wr.sum()), 3))
+    print(f"[fp32 paper cg] {w.name} jacobi={jacobi}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(B, S.SPH_F32, tol=1e-6, variant=S.SPH_CG, jacobi=jacobi, **PAPER)
+    op = oracle_op(w, jacobi=jacobi)
+    Xo, ro, ho = OF.cg_solve(op, B, tol=1e-6)
+    print(f"[fp32 paper cg] iterations GPU {rep['iters']} oracle {ro['iters']}", flush=True)
+    assert rep["status"] == 0 and ro["state"] == [O.CONVERGED] * 3
+    assert abs(rep["iters"] - ro["iters"]) <= max(2, ro["iters"] // 5)
+    assert _is_f32(rep["rr"]) and _is_f32(rep["tau2"]) and _is_f32(rep["history"])
+    assert np.allclose(rep["tau2"], ro["tau2"], rtol=2.0 ** -22, atol=0)
+    h = np.asarray(rep["history"])[:4]
+    assert np.all(np.abs(h / ho[:4] - 1.0) < 1e-3)
+    Xd = O.dense_solve(op, B)
+    assert rel_l2(X, Xd) < 2e-5 and rel_l2(Xo, Xd) < 2e-5
