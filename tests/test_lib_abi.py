@@ -4,6 +4,7 @@ no compute calls."""
 import ctypes as C
 import os
 import subprocess
+import sys
 import tempfile
 
 import pytest
@@ -58,7 +59,7 @@ def test_null_context_is_an_argument_error(lib):
 
 
 STRUCT_NAMES = ["sph_particles", "sph_domain", "sph_visc_params", "sph_solve_opts",
-                "sph_solve_report"]
+                "sph_solve_report", "sph_step_params"]
 # every field of every ctypes mirror, in declaration order
 STRUCTS = {st: [f[0] for f in getattr(S, st)._fields_] for st in STRUCT_NAMES}
 
@@ -81,3 +82,11 @@ def test_ctypes_layout_matches_c():
         assert int(got[st]) == C.sizeof(cls), st
         for f in fields:
             assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: the solver has no multi-GPU decomposition, and the check
+    # comes before anything touches a device
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "--gpus 2" in r.stderr and r.stdout == ""
