@@ -127,3 +127,31 @@ def test_fp32_scalars_cg_parity(ctx, jacobi):
     assert np.all(np.abs(h / ho[:4] - 1.0) < 1e-3)
     Xd = O.dense_solve(op, B)
     assert rel_l2(X, Xd) < 2e-5 and rel_l2(Xo, Xd) < 2e-5
+
+
+def test_fp32_scalars_edge_cases(ctx):
+    # zero right-hand sides converge at once with tau^2 = FLT_MIN; a single
+    # particle is its own solution; a NaN is refused; the iteration cap
+    # returns valid outputs; two runs agree bit for bit
+    w = W.poiseuille(8, wall=W.WALL_DUMMY)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F32, tol=1e-6, **PAPER)
+    assert rep["state"] == [S.SPH_CONVERGED] * 3 and np.all(X[:, 1:] == 0.0)
+    assert rep["tau2"][1] == float(np.finfo(np.float32).tiny) and rep["history"][0][1] == 0.0
+    one = W.Workload("one", np.array([[0.5, 0.5, 0.5]]), np.ones(1), np.ones(1), np.ones(1),
+                     np.zeros(1, np.uint8), np.zeros(3), np.ones(3) * 4, np.array([1, 1, 1]), 0.6,
+                     0.1, 0, 0, np.array([[1.0, -2.0, 0.0]]), None, 1e-8)
+    X1, r1 = GpuCase(ctx, one).solve(one.rhs, S.SPH_F32, **PAPER)
+    assert r1["status"] == 0 and np.array_equal(X1, one.rhs)
+    t = small_tank(seed=53)
+    gt = GpuCase(ctx, t)
+    B = t.rhs.copy()
+    B[7, 2] = np.nan
+    with pytest.raises(S.SphError) as e:
+        gt.solve(B, S.SPH_F32, **PAPER)
+    assert e.value.status == S.SPH_E_NONFINITE
+    Xc, rc = gt.solve(t.rhs, S.SPH_F32, tol=1e-7, max_iter=2, **PAPER)
+    assert rc["status"] == S.SPH_NOT_CONVERGED and rc["iters"] == 2 and np.all(np.isfinite(Xc))
+    a, ra = gt.solve(t.rhs, S.SPH_F32, tol=1e-6, **PAPER)
+    b, rb = gt.solve(t.rhs, S.SPH_F32, tol=1e-6, **PAPER)
+    assert np.array_equal(a, b) and ra["history"] == rb["history"]
