@@ -258,6 +258,25 @@ sph_status sph_visc_apply(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *
                           const sph_visc_params *params, int32_t prec, const void *const x[3],
                           void *const y[3]);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight time-stepping loops, harnesses that forbid hipMalloc.
+ * ------------------------------------------------------------------------ */
+#define SPH_NOALLOC_MAX_N 262144 /* particles; 97 bytes each of staging, 25.4 MB per device */
+/* sph_visc_apply with the on-the-fly operator, allocating nothing: the
+ * cell-order staging of the particle properties, x and y lives in one static
+ * device array of the library (SPH_NOALLOC_MAX_N x 97 bytes, held by each
+ * device the library runs on until the process ends) instead of the
+ * context's workspace.  Arguments, layouts and results are those of
+ * sph_visc_apply (the same kernels, so the same bits); params->op_mode must
+ * be SPH_OP_ONTHEFLY (the cached matrix needs storage that grows with the
+ * system) and nb->n <= SPH_NOALLOC_MAX_N, else SPH_E_ARG.  Asynchronous on
+ * the context stream.  All calls on one device share its array: calls that
+ * overlap on one device (other contexts, other streams) race. */
+sph_status sph_visc_apply_noalloc(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
+                                  const sph_visc_params *params, int32_t prec, const void *const x[3],
+                                  void *const y[3]);
+
 /* Solve A V = B.  nb may be null, then dom must be given and the lists are
  * built inside the call.  rhs[c]: device, n values of the precision (FP64
  * for SPH_MIXED); x[c]: device, n values of the same; initial guess on

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libsph.so")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["capi.hip", "nbr.hip", "operator.hip", "solver.hip", "mlp.hip", "warmstart.hip", "viscosity.hip", "timestep.hip"]
+SOURCES = ["capi.hip", "nbr.hip", "operator.hip", "solver.hip", "mlp.hip", "warmstart.hip", "viscosity.hip", "timestep.hip",
+           "noalloc.hip"]
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas", "-I", INCLUDE, "-I", CSRC]

@@ -45,6 +45,7 @@ extern "C" sph_status sph_create(sph_ctx** out, int32_t device, void* hip_stream
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SPH_E_HIP;
     if (device < 0 || device >= ndev) return SPH_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return SPH_E_HIP;
+    if (sph::noalloc_setup(device) != SPH_OK) return SPH_E_HIP;
     sph_ctx* ctx = new sph_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);

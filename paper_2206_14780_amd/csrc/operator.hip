@@ -67,27 +67,31 @@ __global__ __launch_bounds__(kBlock) void k_scatter_vec3(int64_t n, const int32_
     c[o] = v.z;
 }
 
+sph_status gather_props_into(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, const PropBufs& b,
+                             PartView* out) {
+    const int64_t n = nb->n;
+    hipLaunchKernelGGL(k_gather_props, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
+                       nb->perm, p->mass, p->rho, p->mu, p->type, b.mass, b.rho, b.mu, b.type, b.mu_mr, b.inv_rho);
+    SPH_LAUNCHED("k_gather_props");
+    out->mass = b.mass;
+    out->rho = b.rho;
+    out->mu = b.mu;
+    out->type = b.type;
+    out->mu_mr = b.mu_mr;
+    out->inv_rho = b.inv_rho;
+    return SPH_OK;
+}
+
 sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out) {
     const int64_t n = nb->n;
-    double *m = nullptr, *r = nullptr, *mu = nullptr, *ir = nullptr;
-    double2* mr = nullptr;
-    uint8_t* t = nullptr;
-    SPH_TRY(ctx->ensure_t(kMass, n, &m));
-    SPH_TRY(ctx->ensure_t(kRho, n, &r));
-    SPH_TRY(ctx->ensure_t(kMu, n, &mu));
-    SPH_TRY(ctx->ensure_t(kType, n, &t));
-    SPH_TRY(ctx->ensure_t(kMuMr, n, &mr));
-    SPH_TRY(ctx->ensure_t(kInvRho, n, &ir));
-    hipLaunchKernelGGL(k_gather_props, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
-                       nb->perm, p->mass, p->rho, p->mu, p->type, m, r, mu, t, mr, ir);
-    SPH_LAUNCHED("k_gather_props");
-    out->mass = m;
-    out->rho = r;
-    out->mu = mu;
-    out->type = t;
-    out->mu_mr = mr;
-    out->inv_rho = ir;
-    return SPH_OK;
+    PropBufs b;
+    SPH_TRY(ctx->ensure_t(kMass, n, &b.mass));
+    SPH_TRY(ctx->ensure_t(kRho, n, &b.rho));
+    SPH_TRY(ctx->ensure_t(kMu, n, &b.mu));
+    SPH_TRY(ctx->ensure_t(kType, n, &b.type));
+    SPH_TRY(ctx->ensure_t(kMuMr, n, &b.mu_mr));
+    SPH_TRY(ctx->ensure_t(kInvRho, n, &b.inv_rho));
+    return gather_props_into(ctx, nb, p, b, out);
 }
 
 template <typename S, typename T>

@@ -276,7 +276,17 @@ sph_status scan_i32(sph_ctx* ctx, const int32_t* in, int32_t* out, int64_t n);
 sph_status scan_i64(sph_ctx* ctx, const int64_t* in, int64_t* out, int64_t n);
 
 // Operator pieces (operator.hip).
+// Cell-order copies of the particle properties (n entries each).
+struct PropBufs {
+    double *mass, *rho, *mu, *inv_rho;
+    uint8_t* type;
+    double2* mu_mr;
+};
+// Gathers the properties into the context workspace, or into caller-given
+// buffers (gather_props_into: allocates nothing).
 sph_status gather_props(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, PartView* out);
+sph_status gather_props_into(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, const PropBufs& b,
+                             PartView* out);
 template <typename T>
 sph_status gather_vec3(sph_ctx* ctx, const sph_nbr* nb, const void* const src[3], T* dst);
 // The same from caller arrays of precision S into cell-order T (S = double, T = float).
@@ -297,6 +307,10 @@ sph_status row_diag64(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
                       const double** diag64);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Looks up the device address of the allocation-free entry point's staging
+// array on `device` (which must be current); once per device (noalloc.hip).
+sph_status noalloc_setup(int device);
 
 }  // namespace sph
 

@@ -27,6 +27,7 @@ SPH_KERNEL_WENDLAND, SPH_KERNEL_GAUSSIAN = 0, 1
 SPH_OP_CACHED, SPH_OP_ONTHEFLY = 0, 1
 SPH_CONVERGED, SPH_STATE_STALLED, SPH_PROGRESSING = 0, 1, 2
 SPH_MLP_NPARAM, SPH_MLP_SAMPLE = 8835, 8
+SPH_NOALLOC_MAX_N = 262144
 
 _vp = C.c_void_p
 
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
     L.sph_neighbors_export.argtypes = [_vp, _vp, _vp, _vp, i64, P(i64)]
     L.sph_neighbors_free.argtypes = [_vp]
     L.sph_visc_apply.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp), P(_vp)]
+    L.sph_visc_apply_noalloc.argtypes = [_vp, _vp, P(sph_particles), P(sph_visc_params), i32, P(_vp), P(_vp)]
     L.sph_visc_solve.argtypes = [_vp, _vp, P(sph_domain), P(sph_particles), P(sph_visc_params), i32,
                                  P(_vp), P(_vp), P(sph_solve_opts), P(sph_solve_report)]
     L.sph_visc_papanastasiou.argtypes = [_vp, _vp, P(sph_particles), i32, P(_vp), C.c_double, C.c_double,
@@ -135,6 +137,7 @@ def load(path: str = LIB_PATH):
                                      P(C.c_double)]
     for f in ("sph_create", "sph_destroy", "sph_set_stream", "sph_build_neighbors",
               "sph_neighbors_info", "sph_neighbors_export", "sph_neighbors_free", "sph_visc_apply",
+              "sph_visc_apply_noalloc",
               "sph_visc_solve", "sph_visc_papanastasiou", "sph_semi_implicit_step", "sph_mlp_samples",
               "sph_mlp_warmstart",
               "sph_mlp_forward", "sph_mlp_grad", "sph_mlp_train_step"):
@@ -282,6 +285,14 @@ class Context:
         pc = particles.c()
         self._check(self.L.sph_visc_apply(self.h, nb.h, C.byref(pc), C.byref(params), int(prec), xs,
                                           ys), "sph_visc_apply")
+
+    def sph_visc_apply_noalloc(self, nb: "Neighbors", particles: Particles, params: sph_visc_params,
+                               prec: int, x: Sequence, y: Sequence):
+        xs = (C.c_void_p * 3)(*[_ptr(t) for t in x])
+        ys = (C.c_void_p * 3)(*[_ptr(t) for t in y])
+        pc = particles.c()
+        self._check(self.L.sph_visc_apply_noalloc(self.h, nb.h, C.byref(pc), C.byref(params), int(prec), xs,
+                                                  ys), "sph_visc_apply_noalloc")
 
     # --- sph_visc_papanastasiou ---------------------------------------------
     def sph_visc_papanastasiou(self, nb: "Neighbors", particles: Particles, prec: int, u: Sequence,
