@@ -57,6 +57,7 @@ def lib():
         L.orc_apply.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.POINTER(dp)]
         L.orc_diag.argtypes = [C.POINTER(OrcOp), dp]
         L.orc_assemble_dense.argtypes = [C.POINTER(OrcOp), dp]
+        L.orc_assemble_csr.argtypes = [C.POINTER(OrcOp), dp, dp]
         L.orc_bicgstab.restype = C.c_int32
         L.orc_bicgstab.argtypes = [C.POINTER(OrcOp), C.c_int32, C.POINTER(dp), C.POINTER(dp),
                                    C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_double,
@@ -69,6 +70,11 @@ def lib():
         L.orc_ybar.argtypes = [C.c_double, C.c_double]
         L.orc_papanastasiou.argtypes = [C.POINTER(OrcOp), C.POINTER(dp), C.c_double, C.c_double, C.c_double,
                                         dp, dp]
+        fp = C.POINTER(C.c_float)
+        L.orc_kahan_sum_f32.restype = C.c_float
+        L.orc_kahan_sum_f32.argtypes = [C.c_int64, fp]
+        L.orc_kahan_dot_f32.restype = C.c_float
+        L.orc_kahan_dot_f32.argtypes = [C.c_int64, fp, fp, fp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -83,7 +89,8 @@ class OrcOp(C.Structure):
                 ("mass", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
                 ("mu", C.POINTER(C.c_double)), ("type", C.POINTER(C.c_uint8)),
                 ("dt", C.c_double), ("wall", C.c_int32), ("avg", C.c_int32),
-                ("jacobi", C.c_int32), ("kernel", C.c_int32)]
+                ("jacobi", C.c_int32), ("kernel", C.c_int32),
+                ("a_diag", C.POINTER(C.c_double)), ("a_off", C.POINTER(C.c_double))]
 
 
 class OrcReport(C.Structure):
@@ -104,6 +111,26 @@ def num_threads() -> int:
 
 def set_num_threads(n: int) -> None:
     lib().orc_set_num_threads(int(n))
+
+
+def _fp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def kahan_sum_f32(v) -> np.float32:
+    """Kahan's compensated FP32 sum of v in index order."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    return np.float32(lib().orc_kahan_sum_f32(v.size, _fp(v)))
+
+
+def kahan_dot_f32(a, b, w=None) -> np.float32:
+    """sum_i (w_i) a_i b_i in FP32: products rounded to FP32, then added in
+    index order with Kahan's compensation."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+    return np.float32(lib().orc_kahan_dot_f32(a.size, _fp(w), _fp(a), _fp(b)))
 
 
 def wendland_w(q):
@@ -250,6 +277,25 @@ class Operator:
         A = np.zeros((self.n, self.n))
         lib().orc_assemble_dense(C.byref(self.s), _dp(A))
         return A
+
+    def entries(self):
+        """(diag (n,), off (nnz,)): the entries of A (or D^-1 A) on the
+        neighbour pattern (row_ptr, cols), as the dense assembly forms them."""
+        d = np.zeros(self.n)
+        e = np.zeros(max(int(self.row_ptr[-1]), 1))
+        lib().orc_assemble_csr(C.byref(self.s), _dp(d), _dp(e))
+        return d, e[:int(self.row_ptr[-1])]
+
+    def assemble(self):
+        """Stores the entries once; every later apply (and solve) on this
+        operator then multiplies by them instead of re-evaluating each pair
+        weight.  Returns self."""
+        self._a_diag, self._a_off = self.entries()
+        if self._a_off.size == 0:
+            self._a_off = np.zeros(1)
+        self.s.a_diag = _dp(self._a_diag)
+        self.s.a_off = _dp(self._a_off)
+        return self
 
 
 def solve(op: Operator, B, X0=None, tol=1e-8, max_iter=10000, variant=ROBUST, floor=DBL_MIN,

@@ -17,9 +17,17 @@
  *   - the viscous matrix A(dt), matrix-free and dense
  *                                                 eqs. kab, implicit-system-base, diag,
  *                                                 offdiag, implicit-system-dummy-full
+ *   - the same matrix assembled on the neighbour pattern (stored entries,
+ *     for solves of systems of millions of rows) eqs. diag, offdiag,
+ *                                                 implicit-system-dummy-full
  *   - Jacobi scaling                              appendix "Implementation notes"
+ *   - Kahan's compensated FP32 sums and inner products (the paper's
+ *     single-precision arithmetic)                appendix "Implementation notes"
  *   - robust (restructured) BiCGSTAB and the textbook BiCGSTAB, three systems
- *     sharing one matrix, with the three-state stopping rule
+ *     sharing one matrix, with the three-state stopping rule; the loop is
+ *     organised in the phases direction update, first half-step, second
+ *     half-step, close-out; FP64 inner products are summed in fixed blocks
+ *     (the same result for any thread count)
  *                                                 Section "Restructuring the stabilized
  *                                                 biconjugate gradient method"
  *   - the rotated Conjugate Gradient for the symmetric case (dynamic walls,
@@ -112,6 +120,10 @@
 #define ORC_NOT_CONVERGED 2
 #define ORC_E_ARG (-1)
 #define ORC_E_NONFINITE (-5)
+
+/* loops over particles run in parallel only from this length on (small systems
+ * would spend more on the thread team than on the loop) */
+#define ORC_PAR_MIN 65536
 
 static const double ORC_PI = 3.14159265358979323846;
 
@@ -441,6 +453,12 @@ typedef struct {
     int32_t avg;    /* ORC_AVG_ARITH / ORC_AVG_HARMONIC */
     int32_t jacobi; /* 1: rows scaled by 1/A_bb (appendix "Implementation notes") */
     int32_t kernel; /* ORC_KERNEL_WENDLAND / ORC_KERNEL_GAUSSIAN */
+    /* Optional assembled form (orc_assemble_csr): the matrix entries on the
+     * neighbour pattern, a_diag[b] = A_bb and a_off[k] = A_b,cols[k] (Jacobi
+     * scaled when jacobi is set).  When a_off is non-null orc_apply forms
+     * y = A x from these stored entries instead of re-evaluating them. */
+    const double *a_diag;
+    const double *a_off;
 } orc_op;
 
 #define ORC_KERNEL_WENDLAND 0
@@ -500,6 +518,25 @@ void orc_diag(const orc_op *op, double *d) {
  *   dummy wall row b:   y_b = x_b + sum_{a in F} W_ba x_a / sum_{a in F} W_ba
  *                       (identity when no fluid neighbour)              (eq. implicit-system-dummy-full) */
 void orc_apply(const orc_op *op, const double *const *xin, double *const *yout) {
+    if (op->a_off) {
+        /* y_b = A_bb x_b + sum_k A_b,cols[k] x_cols[k] over the stored entries */
+        #pragma omp parallel for schedule(static)
+        for (int64_t b = 0; b < op->n; ++b) {
+            double d = op->a_diag[b];
+            double y0 = d * xin[0][b], y1 = d * xin[1][b], y2 = d * xin[2][b];
+            for (int64_t k = op->row_ptr[b]; k < op->row_ptr[b + 1]; ++k) {
+                double e = op->a_off[k];
+                int64_t a = op->cols[k];
+                y0 += e * xin[0][a];
+                y1 += e * xin[1][a];
+                y2 += e * xin[2][a];
+            }
+            yout[0][b] = y0;
+            yout[1][b] = y1;
+            yout[2][b] = y2;
+        }
+        return;
+    }
     #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < op->n; ++b) {
         double y0, y1, y2;
@@ -585,6 +622,66 @@ void orc_assemble_dense(const orc_op *op, double *A) {
     }
 }
 
+/* The entries of A (or D^-1 A) on the neighbour pattern, by the same
+ * expressions as the dense assembly: a_diag[b] = A_bb, a_off[k] = A_b,a with
+ * a = cols[k] (0 for the wall neighbours of a dummy-wall row and for every
+ * neighbour of an identity row).  a_off has row_ptr[n] entries. */
+void orc_assemble_csr(const orc_op *op, double *a_diag, double *a_off) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < op->n; ++b) {
+        int64_t k0 = op->row_ptr[b], k1 = op->row_ptr[b + 1];
+        for (int64_t k = k0; k < k1; ++k) a_off[k] = 0.0;
+        if (op->type[b] == ORC_FLUID) {
+            double diag = orc_row_diag(op, b);
+            double scale = op->jacobi ? 1.0 / diag : 1.0;
+            a_diag[b] = op->jacobi ? 1.0 : diag;
+            for (int64_t k = k0; k < k1; ++k) a_off[k] = -op->dt * orc_pair_w(op, b, op->cols[k]) * scale;
+        } else if (op->wall == ORC_WALL_DUMMY) {
+            double sW = 0.0;
+            for (int64_t k = k0; k < k1; ++k)
+                if (op->type[op->cols[k]] == ORC_FLUID) sW += orc_pair_W(op, b, op->cols[k]);
+            a_diag[b] = 1.0;
+            if (sW > 0.0)
+                for (int64_t k = k0; k < k1; ++k)
+                    if (op->type[op->cols[k]] == ORC_FLUID) a_off[k] = orc_pair_W(op, b, op->cols[k]) / sW;
+        } else {
+            a_diag[b] = 1.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-precision compensated sums (appendix "Implementation notes": every */
+/* multi-term sum in single precision uses Kahan's compensated summation).   */
+/* ------------------------------------------------------------------------ */
+
+/* Kahan's compensated sum of v[0..n) in FP32, in index order. */
+float orc_kahan_sum_f32(int64_t n, const float *v) {
+    float s = 0.0f, c = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        float y = v[i] - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    return s;
+}
+
+/* sum_i w_i a_i b_i in FP32: each product rounded to FP32 ((w_i a_i) b_i
+ * when w is given, else a_i b_i), the products added in index order with
+ * Kahan's compensation. */
+float orc_kahan_dot_f32(int64_t n, const float *w, const float *a, const float *b) {
+    float s = 0.0f, c = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        float p = w ? (w[i] * a[i]) * b[i] : a[i] * b[i];
+        float y = p - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    return s;
+}
+
 /* ------------------------------------------------------------------------ */
 /* BiCGSTAB for d = 3 systems sharing one matrix.                            */
 /* ------------------------------------------------------------------------ */
@@ -606,9 +703,29 @@ typedef struct {
 #define ORC_STANDARD 1
 #define ORC_MAX_RESTARTS 3
 
+/* Inner products are summed in fixed blocks of ORC_DOT_BLOCK terms and the
+ * block sums then in block order, so the result does not depend on the
+ * thread count (for n <= ORC_DOT_BLOCK it is the plain sequential sum). */
+#define ORC_DOT_BLOCK 16384
+
 static double orc_dot(int64_t n, const double *a, const double *b) {
+    int64_t nblk = (n + ORC_DOT_BLOCK - 1) / ORC_DOT_BLOCK;
+    if (nblk <= 1) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+        return s;
+    }
+    double *part = (double *)malloc(sizeof(double) * (size_t)nblk);
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t k = 0; k < nblk; ++k) {
+        int64_t i1 = (k + 1) * ORC_DOT_BLOCK < n ? (k + 1) * ORC_DOT_BLOCK : n;
+        double s = 0.0;
+        for (int64_t i = k * ORC_DOT_BLOCK; i < i1; ++i) s += a[i] * b[i];
+        part[k] = s;
+    }
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int64_t k = 0; k < nblk; ++k) s += part[k];
+    free(part);
     return s;
 }
 
@@ -618,12 +735,205 @@ static int orc_finite(double v) { return isfinite(v); }
 static void orc_residual(const orc_op *op, double *const *bh, double *const *x, double *const *r,
                          double *const *tmp) {
     orc_apply(op, (const double *const *)x, tmp);
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+        #pragma omp parallel for schedule(static) if (op->n >= ORC_PAR_MIN)
         for (int64_t i = 0; i < op->n; ++i) r[c][i] = bh[c][i] - tmp[c][i];
+    }
+}
+
+/* State of one BiCGSTAB solve: vectors and per-component scalars. */
+typedef struct {
+    const orc_op *op;
+    int32_t variant;
+    int64_t n;
+    double *bh[3], *r[3], *rh0[3], *p[3], *Ap[3], *s[3], *As[3], *tmp[3];
+    double *const *x;
+    /* robust form: gamma_i, alpha'_{i-1}, beta_{i-1}; textbook form:
+     * gamma_{i-1}, alpha_{i-1}, omega_{i-1} (in gamma_prev, alpha, omega) */
+    double gamma[3], gamma_prev[3], alpha[3], alphap[3], beta[3], omega[3], delta[3];
+    double tau2[3], rr[3], rr_ref[3];
+    int state[3], restarts[3], stall[3];
+} orc_bicg;
+
+static void orc_bicg_fresh_direction(orc_bicg *S, int c) {
+    /* the next direction is built from r alone */
+    S->alphap[c] = 0.0;
+    S->beta[c] = 0.0;
+    S->gamma_prev[c] = 1.0;
+    S->alpha[c] = 1.0;
+    S->omega[c] = 1.0;
+}
+
+/* Direction update.  Robust form: p = r + beta p - alpha' A p, a term with
+ * a zero coefficient skipped so that p and A p need not be defined at the
+ * first iteration.  Textbook form: gamma = r0hat . r, beta =
+ * (gamma / gamma_prev)(alpha / omega), p = r + beta (p - omega A p), and a
+ * zero gamma is a breakdown. */
+static void orc_bicg_direction(orc_bicg *S) {
+    int64_t n = S->n;
+    for (int c = 0; c < 3; ++c) {
+        double *p = S->p[c];
+        const double *r = S->r[c], *Ap = S->Ap[c];
+        if (S->variant == ORC_ROBUST) {
+            double bt = S->beta[c], ap = S->alphap[c];
+            #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+            for (int64_t i = 0; i < n; ++i) {
+                double v = r[i];
+                if (bt != 0.0) v += bt * p[i];
+                if (ap != 0.0) v -= ap * Ap[i];
+                p[i] = v;
+            }
+        } else {
+            double g = orc_dot(n, S->rh0[c], r);
+            double bt = 0.0;
+            if (S->gamma_prev[c] != 0.0 && S->omega[c] != 0.0)
+                bt = (g / S->gamma_prev[c]) * (S->alpha[c] / S->omega[c]);
+            if (!orc_finite(bt)) bt = 0.0;
+            if (g == 0.0) S->stall[c] = 1;
+            S->gamma[c] = g;
+            S->beta[c] = bt;
+            double om = S->omega[c];
+            #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+            for (int64_t i = 0; i < n; ++i) {
+                double v = r[i];
+                if (bt != 0.0) v += bt * (p[i] - om * Ap[i]);
+                p[i] = v;
+            }
+        }
+    }
+}
+
+/* First half-step: A p, delta = r0hat . A p, alpha = gamma / delta (a zero
+ * or non-finite delta or alpha is a breakdown, alpha = 0), and the
+ * intermediate residual s = r - alpha A p. */
+static void orc_bicg_half1(orc_bicg *S, int it, int32_t force_stall_iter, int32_t force_stall_comp) {
+    int64_t n = S->n;
+    orc_apply(S->op, (const double *const *)S->p, S->Ap);
+    for (int c = 0; c < 3; ++c) {
+        double d = orc_dot(n, S->rh0[c], S->Ap[c]);
+        if (it == force_stall_iter && c == force_stall_comp) d = 0.0;
+        double a = 0.0;
+        if (d != 0.0 && orc_finite(d)) a = S->gamma[c] / d;
+        if (!orc_finite(a) || d == 0.0 || !orc_finite(d)) {
+            a = 0.0;
+            S->stall[c] = 1;
+        }
+        S->delta[c] = d;
+        S->alpha[c] = a;
+        double *sv = S->s[c];
+        const double *r = S->r[c], *Ap = S->Ap[c];
+        #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+        for (int64_t i = 0; i < n; ++i) sv[i] = r[i] - a * Ap[i];
+    }
+}
+
+/* Second half-step: A s, omega = (s . A s)/(A s . A s) (zero: breakdown);
+ * the textbook form also checks s itself and takes omega = 0 when s . s
+ * already meets the threshold; then x = x + alpha p + omega s and
+ * r = s - omega A s. */
+static void orc_bicg_half2(orc_bicg *S) {
+    int64_t n = S->n;
+    orc_apply(S->op, (const double *const *)S->s, S->As);
+    for (int c = 0; c < 3; ++c) {
+        double tt = orc_dot(n, S->As[c], S->As[c]);
+        double ts = orc_dot(n, S->As[c], S->s[c]);
+        double w = 0.0;
+        if (tt != 0.0) w = ts / tt;
+        if (!orc_finite(w)) w = 0.0;
+        if (w == 0.0) S->stall[c] = 1;
+        if (S->variant == ORC_STANDARD && orc_dot(n, S->s[c], S->s[c]) < S->tau2[c]) w = 0.0;
+        S->omega[c] = w;
+        double a = S->alpha[c];
+        double *x = S->x[c], *r = S->r[c];
+        const double *p = S->p[c], *sv = S->s[c], *As = S->As[c];
+        #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+        for (int64_t i = 0; i < n; ++i) {
+            double xv = x[i] + a * p[i];
+            x[i] = xv + w * sv[i];
+            r[i] = sv[i] - w * As[i];
+        }
+    }
+}
+
+/* Close-out.  Robust form: gamma' = r0hat . r, alpha' = gamma'/delta,
+ * beta = alpha'/omega (both 0 after a breakdown; a zero gamma' is one);
+ * textbook form: keep gamma for the next beta.  Then r . r and the state:
+ * converged when r . r < tau^2 (taking precedence), stalled after a
+ * breakdown, progressing otherwise. */
+static void orc_bicg_close(orc_bicg *S, orc_report *rep) {
+    int64_t n = S->n;
+    for (int c = 0; c < 3; ++c) {
+        if (S->variant == ORC_ROBUST) {
+            double g = orc_dot(n, S->rh0[c], S->r[c]);
+            double ap = 0.0, bt = 0.0;
+            if (!S->stall[c]) {
+                ap = g / S->delta[c];
+                if (!orc_finite(ap)) ap = 0.0;
+                bt = ap / S->omega[c];
+                if (!orc_finite(bt)) bt = 0.0;
+            }
+            if (g == 0.0) S->stall[c] = 1;
+            S->gamma[c] = g;
+            S->alphap[c] = ap;
+            S->beta[c] = bt;
+        } else {
+            S->gamma_prev[c] = S->gamma[c];
+        }
+        S->rr[c] = orc_dot(n, S->r[c], S->r[c]);
+        if (S->stall[c]) rep->stall_count[c]++;
+        S->state[c] = S->rr[c] < S->tau2[c] ? ORC_CONVERGED : (S->stall[c] ? ORC_STALLED : ORC_PROGRESSING);
+    }
+}
+
+/* True residual check: r_true = bh - Ah x; a component the recursion calls
+ * converged but r_true does not is restarted from r_true (at most
+ * ORC_MAX_RESTARTS times, then reported stalled); with restart_drop > 0 a
+ * progressing component whose true r.r fell below restart_drop times its
+ * r.r at the last (re)start restarts the same way.  A restart takes
+ * r = r0hat = r_true and a fresh direction. */
+static void orc_bicg_check(orc_bicg *S, double restart_drop, orc_report *rep) {
+    int64_t n = S->n;
+    rep->n_true_checks++;
+    orc_residual(S->op, S->bh, S->x, S->tmp, S->s);
+    for (int c = 0; c < 3; ++c) {
+        double trr = orc_dot(n, S->tmp[c], S->tmp[c]);
+        int restart = 0;
+        if (S->state[c] == ORC_CONVERGED && !(trr < S->tau2[c])) {
+            if (S->restarts[c] >= ORC_MAX_RESTARTS) {
+                S->state[c] = ORC_STALLED; /* precision cannot reach the tolerance */
+            } else {
+                S->restarts[c]++;
+                restart = 1;
+            }
+        } else if (S->state[c] == ORC_PROGRESSING && trr < restart_drop * S->rr_ref[c]) {
+            restart = 1; /* residual far below the shadow vector: fresh start */
+        }
+        if (restart) {
+            memcpy(S->r[c], S->tmp[c], sizeof(double) * (size_t)n);
+            memcpy(S->rh0[c], S->tmp[c], sizeof(double) * (size_t)n);
+            S->rr[c] = trr;
+            S->gamma[c] = orc_dot(n, S->rh0[c], S->r[c]);
+            orc_bicg_fresh_direction(S, c);
+            memset(S->p[c], 0, sizeof(double) * (size_t)n);
+            memset(S->Ap[c], 0, sizeof(double) * (size_t)n);
+            S->state[c] = trr < S->tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+            S->rr_ref[c] = trr;
+            rep->n_replaced++;
+        }
+    }
+}
+
+static int orc_bicg_any_progressing(const orc_bicg *S) {
+    int any = 0;
+    for (int c = 0; c < 3; ++c) any |= (S->state[c] == ORC_PROGRESSING);
+    return any;
 }
 
 /*
- * Solve A V = B for the three columns of B.  With op->jacobi the system is
+ * Solve A V = B for the three columns of B by the restructured ("robust")
+ * BiCGSTAB or the textbook BiCGSTAB (Section "Restructuring the stabilized
+ * biconjugate gradient method"), each component with its own scalars and
+ * the stopping rule of that Section.  With op->jacobi the system is
  * left-scaled: Ah = D^-1 A, bh = D^-1 b (appendix "Implementation notes"),
  * and every threshold refers to the scaled residual.
  *
@@ -643,201 +953,76 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
     int64_t n = op->n;
     memset(rep, 0, sizeof(*rep));
     double *buf = (double *)calloc((size_t)(n > 0 ? n : 1) * 3 * 9, sizeof(double));
-    double *bh[3], *r[3], *rh0[3], *p[3], *Ap[3], *s[3], *As[3], *tmp[3], *D[3];
+    orc_bicg S;
+    memset(&S, 0, sizeof(S));
+    S.op = op;
+    S.variant = variant;
+    S.n = n;
+    S.x = x;
+    double *D = buf + 8 * 3 * n;
     for (int c = 0; c < 3; ++c) {
-        bh[c] = buf + (0 * 3 + c) * n;
-        r[c] = buf + (1 * 3 + c) * n;
-        rh0[c] = buf + (2 * 3 + c) * n;
-        p[c] = buf + (3 * 3 + c) * n;
-        Ap[c] = buf + (4 * 3 + c) * n;
-        s[c] = buf + (5 * 3 + c) * n;
-        As[c] = buf + (6 * 3 + c) * n;
-        tmp[c] = buf + (7 * 3 + c) * n;
-        D[c] = buf + (8 * 3 + c) * n;
+        S.bh[c] = buf + (0 * 3 + c) * n;
+        S.r[c] = buf + (1 * 3 + c) * n;
+        S.rh0[c] = buf + (2 * 3 + c) * n;
+        S.p[c] = buf + (3 * 3 + c) * n;
+        S.Ap[c] = buf + (4 * 3 + c) * n;
+        S.s[c] = buf + (5 * 3 + c) * n;
+        S.As[c] = buf + (6 * 3 + c) * n;
+        S.tmp[c] = buf + (7 * 3 + c) * n;
     }
     /* Jacobi: D = diag(A); bh = b / D. */
-    if (op->jacobi) orc_diag(op, D[0]);
+    if (op->jacobi) orc_diag(op, D);
     for (int c = 0; c < 3; ++c)
-        for (int64_t i = 0; i < n; ++i) bh[c][i] = op->jacobi ? b[c][i] / D[0][i] : b[c][i];
-
-    double gamma[3], gamma_prev[3], alpha[3], alphap[3], beta[3], omega[3], delta[3], tau2[3], rr[3];
-    int state[3], restarts[3] = {0, 0, 0};
-    double rr_ref[3];
+        for (int64_t i = 0; i < n; ++i) S.bh[c][i] = op->jacobi ? b[c][i] / D[i] : b[c][i];
     for (int c = 0; c < 3; ++c) {
-        rep->bb[c] = orc_dot(n, bh[c], bh[c]);
+        rep->bb[c] = orc_dot(n, S.bh[c], S.bh[c]);
         if (!orc_finite(rep->bb[c])) {
             free(buf);
             rep->status = ORC_E_NONFINITE;
             return ORC_E_NONFINITE;
         }
     }
-    /* r0 = bh - Ah x0; r0hat = r0; tau^2 = max(eps^2 bh.bh, floor). */
-    orc_residual(op, bh, x, r, tmp);
-    int hl = 0;
+    /* r0 = bh - Ah x0; r0hat = r0; tau^2 = max(eps^2 bh.bh, floor); the
+     * robust form starts with gamma_1 = r0hat . r0 */
+    orc_residual(op, S.bh, x, S.r, S.tmp);
     for (int c = 0; c < 3; ++c) {
-        memcpy(rh0[c], r[c], sizeof(double) * (size_t)n);
-        tau2[c] = tol * tol * rep->bb[c];
-        if (tau2[c] < floor_) tau2[c] = floor_;
-        rr[c] = orc_dot(n, r[c], r[c]);
-        rr_ref[c] = rr[c];
-        gamma[c] = orc_dot(n, rh0[c], r[c]);
-        alphap[c] = 0.0;
-        beta[c] = 0.0;
-        /* textbook start: gamma_0 = alpha_0 = omega_0 = 1, p_0 = v_0 = 0 */
-        gamma_prev[c] = 1.0;
-        alpha[c] = 1.0;
-        omega[c] = 1.0;
-        delta[c] = 0.0;
-        state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
-        if (history && hl < history_cap) history[3 * hl + c] = rr[c];
+        memcpy(S.rh0[c], S.r[c], sizeof(double) * (size_t)n);
+        S.tau2[c] = tol * tol * rep->bb[c];
+        if (S.tau2[c] < floor_) S.tau2[c] = floor_;
+        S.rr[c] = orc_dot(n, S.r[c], S.r[c]);
+        S.rr_ref[c] = S.rr[c];
+        S.gamma[c] = orc_dot(n, S.rh0[c], S.r[c]);
+        orc_bicg_fresh_direction(&S, c);
+        S.delta[c] = 0.0;
+        S.state[c] = S.rr[c] < S.tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
+        if (history && history_cap > 0) history[c] = S.rr[c];
     }
-    hl = 1;
-
+    int hl = 1;
     int it = 0;
     for (;;) {
-        int any_prog = 0;
-        for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
         int periodic_check = (it > 0 && true_res_period > 0 && it % true_res_period == 0);
-        if (!any_prog || periodic_check) {
-            /* True residual; restart converged components that fail it. */
-            rep->n_true_checks++;
-            orc_residual(op, bh, x, tmp, s);
-            for (int c = 0; c < 3; ++c) {
-                double trr = orc_dot(n, tmp[c], tmp[c]);
-                int restart = 0;
-                if (state[c] == ORC_CONVERGED && !(trr < tau2[c])) {
-                    if (restarts[c] >= ORC_MAX_RESTARTS) {
-                        state[c] = ORC_STALLED; /* precision cannot reach the tolerance */
-                    } else {
-                        restarts[c]++;
-                        restart = 1;
-                    }
-                } else if (state[c] == ORC_PROGRESSING && trr < restart_drop * rr_ref[c]) {
-                    restart = 1; /* residual far below the shadow vector: fresh start */
-                }
-                if (restart) {
-                    memcpy(r[c], tmp[c], sizeof(double) * (size_t)n);
-                    memcpy(rh0[c], tmp[c], sizeof(double) * (size_t)n);
-                    rr[c] = trr;
-                    gamma[c] = orc_dot(n, rh0[c], r[c]);
-                    alphap[c] = 0.0;
-                    beta[c] = 0.0;
-                    gamma_prev[c] = 1.0;
-                    alpha[c] = 1.0;
-                    omega[c] = 1.0;
-                    memset(p[c], 0, sizeof(double) * (size_t)n);
-                    memset(Ap[c], 0, sizeof(double) * (size_t)n);
-                    state[c] = trr < tau2[c] ? ORC_CONVERGED : ORC_PROGRESSING;
-                    rr_ref[c] = trr;
-                    rep->n_replaced++;
-                }
-            }
-            any_prog = 0;
-            for (int c = 0; c < 3; ++c) any_prog |= (state[c] == ORC_PROGRESSING);
-        }
-        if (!any_prog || it >= max_iter) break;
+        if (!orc_bicg_any_progressing(&S) || periodic_check) orc_bicg_check(&S, restart_drop, rep);
+        if (!orc_bicg_any_progressing(&S) || it >= max_iter) break;
         ++it;
-        int stall[3] = {0, 0, 0};
-
-        if (variant == ORC_ROBUST) {
-            /* p_i = r_{i-1} + beta_{i-1} p_{i-1} - alpha'_{i-1} A p_{i-1};
-             * a term with a zero coefficient is skipped (p, Ap unread). */
-            for (int c = 0; c < 3; ++c)
-                for (int64_t i = 0; i < n; ++i) {
-                    double v = r[c][i];
-                    if (beta[c] != 0.0) v += beta[c] * p[c][i];
-                    if (alphap[c] != 0.0) v -= alphap[c] * Ap[c][i];
-                    p[c][i] = v;
-                }
-        } else {
-            /* gamma_i = r0hat . r_{i-1}; beta_i = (gamma_i/gamma_{i-1})(alpha_{i-1}/omega_{i-1});
-             * p_i = r_{i-1} + beta_i (p_{i-1} - omega_{i-1} A p_{i-1}). */
-            for (int c = 0; c < 3; ++c) {
-                double g = orc_dot(n, rh0[c], r[c]);
-                double bt = 0.0;
-                if (gamma_prev[c] != 0.0 && omega[c] != 0.0) bt = (g / gamma_prev[c]) * (alpha[c] / omega[c]);
-                if (!orc_finite(bt)) bt = 0.0;
-                if (g == 0.0) stall[c] = 1;
-                gamma[c] = g;
-                beta[c] = bt;
-                for (int64_t i = 0; i < n; ++i) {
-                    double v = r[c][i];
-                    if (bt != 0.0) v += bt * (p[c][i] - omega[c] * Ap[c][i]);
-                    p[c][i] = v;
-                }
-            }
-        }
-        /* A p_i and delta_i = r0hat . A p_i; alpha_i = gamma_i / delta_i. */
-        orc_apply(op, (const double *const *)p, Ap);
-        for (int c = 0; c < 3; ++c) {
-            delta[c] = orc_dot(n, rh0[c], Ap[c]);
-            if (it == force_stall_iter && c == force_stall_comp) delta[c] = 0.0;
-            double a = 0.0;
-            if (delta[c] != 0.0 && orc_finite(delta[c])) a = gamma[c] / delta[c];
-            if (!orc_finite(a) || delta[c] == 0.0 || !orc_finite(delta[c])) {
-                a = 0.0;
-                stall[c] = 1;
-            }
-            alpha[c] = a;
-            /* r_star = r_{i-1} - alpha_i A p_i */
-            for (int64_t i = 0; i < n; ++i) s[c][i] = r[c][i] - a * Ap[c][i];
-        }
-        /* omega_i = (r_star . A r_star) / (A r_star . A r_star) */
-        orc_apply(op, (const double *const *)s, As);
-        for (int c = 0; c < 3; ++c) {
-            double tt = orc_dot(n, As[c], As[c]);
-            double ts = orc_dot(n, As[c], s[c]);
-            double w = 0.0;
-            if (tt != 0.0) w = ts / tt;
-            if (!orc_finite(w)) w = 0.0;
-            if (w == 0.0) stall[c] = 1;
-            if (variant == ORC_STANDARD) {
-                double ss = orc_dot(n, s[c], s[c]);
-                if (ss < tau2[c]) w = 0.0; /* x_star already meets the threshold */
-            }
-            omega[c] = w;
-            /* x_i = x_{i-1} + alpha_i p_i + omega_i r_star; r_i = r_star - omega_i A r_star */
-            for (int64_t i = 0; i < n; ++i) {
-                double xv = x[c][i] + alpha[c] * p[c][i];
-                x[c][i] = xv + w * s[c][i];
-                r[c][i] = s[c][i] - w * As[c][i];
-            }
-        }
-        for (int c = 0; c < 3; ++c) {
-            if (variant == ORC_ROBUST) {
-                /* gamma_{i+1} = r0hat . r_i; alpha'_i = gamma_{i+1}/delta_i; beta_i = alpha'_i/omega_i */
-                double g = orc_dot(n, rh0[c], r[c]);
-                double ap = 0.0, bt = 0.0;
-                if (!stall[c]) {
-                    ap = g / delta[c];
-                    if (!orc_finite(ap)) ap = 0.0;
-                    bt = ap / omega[c];
-                    if (!orc_finite(bt)) bt = 0.0;
-                }
-                if (g == 0.0) stall[c] = 1;
-                gamma[c] = g;
-                alphap[c] = ap;
-                beta[c] = bt;
-            } else {
-                gamma_prev[c] = gamma[c];
-            }
-            rr[c] = orc_dot(n, r[c], r[c]);
-            if (stall[c]) rep->stall_count[c]++;
-            state[c] = rr[c] < tau2[c] ? ORC_CONVERGED : (stall[c] ? ORC_STALLED : ORC_PROGRESSING);
-            if (history && hl < history_cap) history[3 * hl + c] = rr[c];
-        }
+        for (int c = 0; c < 3; ++c) S.stall[c] = 0;
+        orc_bicg_direction(&S);
+        orc_bicg_half1(&S, it, force_stall_iter, force_stall_comp);
+        orc_bicg_half2(&S);
+        orc_bicg_close(&S, rep);
+        if (history && hl < history_cap)
+            for (int c = 0; c < 3; ++c) history[3 * hl + c] = S.rr[c];
         ++hl;
     }
     /* final true residual for the report */
-    orc_residual(op, bh, x, tmp, s);
+    orc_residual(op, S.bh, x, S.tmp, S.s);
     int any_prog = 0, any_stall = 0;
     for (int c = 0; c < 3; ++c) {
-        rep->true_rr[c] = orc_dot(n, tmp[c], tmp[c]);
-        rep->rr[c] = rr[c];
-        rep->tau2[c] = tau2[c];
-        rep->state[c] = state[c];
-        any_prog |= state[c] == ORC_PROGRESSING;
-        any_stall |= state[c] == ORC_STALLED;
+        rep->true_rr[c] = orc_dot(n, S.tmp[c], S.tmp[c]);
+        rep->rr[c] = S.rr[c];
+        rep->tau2[c] = S.tau2[c];
+        rep->state[c] = S.state[c];
+        any_prog |= S.state[c] == ORC_PROGRESSING;
+        any_stall |= S.state[c] == ORC_STALLED;
     }
     rep->iters = it;
     rep->history_len = hl < history_cap ? hl : history_cap;
@@ -853,8 +1038,19 @@ int orc_bicgstab(const orc_op *op, int32_t variant, const double *const *b, doub
 
 /* <a, b>_D = sum_i D_i a_i b_i (D = NULL: the Euclidean product). */
 static double orc_dot_w(int64_t n, const double *D, const double *a, const double *b) {
+    /* blocked like orc_dot: the same result for any thread count */
+    int64_t nblk = (n + ORC_DOT_BLOCK - 1) / ORC_DOT_BLOCK;
+    double *part = (double *)malloc(sizeof(double) * (size_t)(nblk > 0 ? nblk : 1));
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t k = 0; k < nblk; ++k) {
+        int64_t i1 = (k + 1) * ORC_DOT_BLOCK < n ? (k + 1) * ORC_DOT_BLOCK : n;
+        double s = 0.0;
+        for (int64_t i = k * ORC_DOT_BLOCK; i < i1; ++i) s += (D ? D[i] : 1.0) * a[i] * b[i];
+        part[k] = s;
+    }
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += (D ? D[i] : 1.0) * a[i] * b[i];
+    for (int64_t k = 0; k < nblk; ++k) s += part[k];
+    free(part);
     return s;
 }
 
@@ -955,8 +1151,13 @@ int orc_cg(const orc_op *op, const double *const *b, double *const *x, double to
         ++it;
         int stall[3] = {0, 0, 0};
         /* p_i = r_i + beta_i p_{i-1} */
-        for (int c = 0; c < 3; ++c)
-            for (int64_t i = 0; i < n; ++i) p[c][i] = beta[c] != 0.0 ? r[c][i] + beta[c] * p[c][i] : r[c][i];
+        for (int c = 0; c < 3; ++c) {
+            double bt = beta[c];
+            double *pc = p[c];
+            const double *rc = r[c];
+            #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+            for (int64_t i = 0; i < n; ++i) pc[i] = bt != 0.0 ? rc[i] + bt * pc[i] : rc[i];
+        }
         orc_apply(op, (const double *const *)p, Ap);
         for (int c = 0; c < 3; ++c) {
             double pap = orc_dot_w(n, D, p[c], Ap[c]);
@@ -967,9 +1168,12 @@ int orc_cg(const orc_op *op, const double *const *b, double *const *x, double to
                 a = 0.0;
                 stall[c] = 1;
             }
+            double *xc = x[c], *rc = r[c];
+            const double *pc = p[c], *apc = Ap[c];
+            #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
             for (int64_t i = 0; i < n; ++i) {
-                x[c][i] = x[c][i] + a * p[c][i];
-                r[c][i] = r[c][i] - a * Ap[c][i];
+                xc[i] = xc[i] + a * pc[i];
+                rc[i] = rc[i] - a * apc[i];
             }
             double rho_new = orc_dot_w(n, D, r[c], r[c]);
             double bt = 0.0;

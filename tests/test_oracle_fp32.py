@@ -108,3 +108,89 @@ def test_fp32_cg_forced_stall_and_dummy_walls_refused():
     kw, _ = _tank(wall=W.WALL_DUMMY)
     with pytest.raises(ValueError):
         OF.cg_solve(O.Operator(jacobi=True, **kw), B)
+
+
+# --- the paper's compensated single-precision sums (appendix "Implementation
+# notes": Kahan's summation for every multi-term sum) -------------------------
+
+def test_kahan_dot_rounds_each_product_to_fp32():
+    # (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24 lies half-way between two FP32
+    # neighbours and rounds to the even one, 1 + 2^-11, which the second
+    # product cancels exactly: the paper's arithmetic gives 0.  The FP64 sum of
+    # the exact products keeps the 2^-24 that the rounding dropped.
+    a = np.array([1.0 + 2.0 ** -12, -1.0], dtype=np.float32)
+    b = np.array([1.0 + 2.0 ** -12, 1.0 + 2.0 ** -11], dtype=np.float32)
+    assert O.kahan_dot_f32(a, b) == np.float32(0.0)
+    A, B = a[:, None], b[:, None]
+    assert OF._dot(A, B, "kahan")[0] == np.float32(0.0)
+    assert OF._dot(A, B, "f64")[0] == np.float32(2.0 ** -24)
+
+
+def test_kahan_sum_keeps_what_plain_fp32_drops():
+    # 1 followed by 2^20 terms of 2^-24 (half a unit in the last place of 1):
+    # a plain FP32 sum rounds each addition back to 1 (ties to even); the
+    # exact sum 1 + 2^-4 is representable and Kahan's compensation reaches it.
+    v = np.concatenate([[1.0], np.full(1 << 20, 2.0 ** -24)]).astype(np.float32)
+    plain = np.float32(1.0)
+    for t in (v[1], v[2], v[3]):
+        plain = np.float32(plain + t)
+    assert plain == np.float32(1.0)
+    assert O.kahan_sum_f32(v) == np.float32(1.0625)
+    ones = np.ones_like(v)
+    assert O.kahan_dot_f32(v, ones) == np.float32(1.0625)
+
+
+def test_kahan_dot_within_its_error_bound():
+    # |Kahan - exact| <= (2u + 2 n u^2) sum |p_i| over the FP32 products p_i
+    # (u = 2^-24), the exact sum of the products taken in rational arithmetic;
+    # a plain FP32 running sum of the same products errs far more on this data.
+    from fractions import Fraction
+    rng = np.random.default_rng(17)
+    n = 20000
+    a = (rng.normal(size=n) * 10.0 ** rng.uniform(-3, 3, n)).astype(np.float32)
+    b = rng.normal(size=n).astype(np.float32)
+    p = a * b  # FP32 products, each correctly rounded
+    exact = sum(Fraction(float(t)) for t in p)
+    mag = float(np.abs(p.astype(np.float64)).sum())
+    u = 2.0 ** -24
+    k = O.kahan_dot_f32(a, b)
+    err_k = abs(float(Fraction(float(k)) - exact))
+    assert err_k <= (2 * u + 2 * n * u * u) * mag
+    plain = np.float32(0.0)
+    for t in p:
+        plain = np.float32(plain + t)
+    err_p = abs(float(Fraction(float(plain)) - exact))
+    assert err_p > 10.0 * err_k
+    w = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    pw = (w * a) * b
+    exact_w = sum(Fraction(float(t)) for t in pw)
+    kw = O.kahan_dot_f32(a, b, w)
+    assert abs(float(Fraction(float(kw)) - exact_w)) <= (2 * u + 2 * n * u * u) * float(np.abs(pw.astype(np.float64)).sum())
+
+
+@pytest.mark.parametrize("variant", [O.ROBUST, O.STANDARD])
+def test_kahan_form_solves_and_differs_from_the_rounded_once_form(variant):
+    op, B = _case(mu_span=100.0, dt_nu=10.0)
+    X, rep, h = OF.solve(op, B, tol=1e-6, variant=variant, dots="kahan")
+    assert X.dtype == np.float32 and h.dtype == np.float32
+    assert rep["state"] == [O.CONVERGED] * 3
+    assert all(np.float32(v) == v for v in rep["rr"] + rep["tau2"])
+    Xd = O.dense_solve(op, B)
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 2e-5
+    _, _, h64 = OF.solve(op, B, tol=1e-6, variant=variant, dots="f64")
+    # the same iteration: the first residuals agree to FP32 rounding ...
+    assert np.allclose(h[:3], h64[:3], rtol=1e-4, atol=0)
+    # ... but it is a different arithmetic, not the other form under a new name
+    k = min(len(h), len(h64))
+    assert not np.array_equal(h[:k], h64[:k])
+
+
+def test_kahan_form_cg():
+    k, pt = _tank(seed=4, wall=W.WALL_DYNAMIC, avg=W.AVG_HARMONIC, mu_span=1.0, dt_nu=20.0)
+    k["mass"] = np.ones(pt.size)
+    op = O.Operator(jacobi=True, **k)
+    B = np.random.default_rng(4).normal(size=(pt.size, 3))
+    X, rep, h = OF.cg_solve(op, B, tol=1e-6, dots="kahan")
+    assert rep["state"] == [O.CONVERGED] * 3
+    Xd = O.dense_solve(op, B)
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 2e-5

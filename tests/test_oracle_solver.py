@@ -187,3 +187,67 @@ def test_restart_on_drop_still_reaches_the_direct_answer():
     assert rep["status"] == 0 and rep["n_replaced"] >= 3 and rep0["n_replaced"] == 0
     Xd = O.dense_solve(op, B)
     assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 1e-10
+
+
+def _periodic_lattice(n=8, dt=1.8):
+    """All-fluid cubic lattice, periodic on every axis, uniform properties:
+    the operator commutes with lattice translations and reflections, so the
+    constant field and cos(2 pi x / L) are exact eigenvectors."""
+    g = np.arange(n, dtype=np.float64)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    N = pos.shape[0]
+    L = float(n)
+    kw = dict(pos=pos, mass=np.ones(N), rho=np.ones(N), mu=np.ones(N), ptype=np.zeros(N, np.uint8),
+              period=(L, L, L), h=1.3, dt=dt, wall=W.WALL_DYNAMIC, avg=W.AVG_ARITH, lo=np.zeros(3))
+    return kw, pos, L
+
+
+def test_textbook_half_step_check_fires_with_the_hand_computed_iterate():
+    # b = v1 + eta v2 with A v1 = v1 (rows sum to one) and A v2 = lam v2.
+    # From x0 = 0 the first half-step gives, in closed form,
+    #   gamma = b.b = N + eta^2 N/2,  delta = b.Ab = N + eta^2 lam N/2,
+    #   alpha = gamma/delta,  s = (1 - alpha) v1 + eta (1 - alpha lam) v2,
+    #   s.s = (1 - alpha)^2 N + eta^2 (1 - alpha lam)^2 N/2.
+    # With eta = 1e-3 and eps = 1e-3, s.s is below tau^2 = eps^2 b.b while
+    # r0.r0 is not, so the textbook form must stop after its first half-step:
+    # omega = 0, x1 = alpha b, r1 = s (Section "Restructuring the stabilized
+    # biconjugate gradient method", the textbook listing's check after x*).
+    # Without the check the iterate would move by omega s, about s/lam.
+    kw, pos, L = _periodic_lattice()
+    op = O.Operator(jacobi=False, **kw)
+    N = pos.shape[0]
+    v1 = np.ones(N)
+    v2 = np.cos(2.0 * np.pi * pos[:, 0] / L)
+    Av2 = op.apply(np.stack([v2] * 3, axis=1))[:, 0]
+    lam = float(v2 @ Av2 / (v2 @ v2))
+    assert np.max(np.abs(Av2 - lam * v2)) < 1e-12 * lam  # an exact eigenvector
+    assert 1.5 < lam < 3.0                                # s is not negligible
+    eta = 1e-3
+    tol = 1e-3
+    B = np.zeros((N, 3))
+    B[:, 0] = v1 + eta * v2          # the check fires
+    B[:, 1] = v1 + 0.5 * v2          # it does not (s far above the threshold)
+    B[:, 2] = v1 - 0.5 * eta * v2
+    X, rep, hist = O.solve(op, B, tol=tol, max_iter=1, variant=O.STANDARD, true_res_period=0)
+    gamma = N + eta ** 2 * N / 2.0
+    delta = N + eta ** 2 * lam * N / 2.0
+    alpha = gamma / delta
+    ss = (1.0 - alpha) ** 2 * N + eta ** 2 * (1.0 - alpha * lam) ** 2 * N / 2.0
+    assert ss < tol ** 2 * gamma < N                      # the case is as intended
+    assert rep["iters"] == 1 and rep["state"][0] == O.CONVERGED
+    assert np.allclose(X[:, 0], alpha * B[:, 0], rtol=1e-13, atol=1e-13)
+    assert abs(hist[1, 0] - ss) <= 1e-9 * ss               # r1 = s
+    eta2 = -0.5 * eta
+    g2 = N + eta2 ** 2 * N / 2.0
+    a2 = g2 / (N + eta2 ** 2 * lam * N / 2.0)
+    assert np.allclose(X[:, 2], a2 * B[:, 2], rtol=1e-13, atol=1e-13)
+    # the robust form has no such check: its first iterate adds omega s
+    Xr, repr_, histr = O.solve(op, B, tol=tol, max_iter=1, variant=O.ROBUST, true_res_period=0)
+    s = B[:, 0] - alpha * (v1 + eta * lam * v2)
+    omega = 1.0 / lam  # s lies in span(v1, v2) with its v2 part dominant
+    assert np.linalg.norm(Xr[:, 0] - X[:, 0]) > 0.5 * abs(omega) * np.linalg.norm(s)
+    assert histr[1, 0] < 1e-3 * ss
+    # where the check does not fire the two forms take the same first step
+    assert hist[1, 1] > tol ** 2 * (B[:, 1] @ B[:, 1])
+    assert np.allclose(X[:, 1], Xr[:, 1], rtol=1e-12, atol=1e-14)
+    assert abs(hist[1, 1] - histr[1, 1]) <= 1e-10 * hist[1, 1]
