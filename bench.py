@@ -1,25 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the semi-implicit SPH viscous solve on one MI355X.
 
-Workload: the 100^3 jittered open-top tank (1,157,308 particles with three
-wall layers, dummy walls, nu = 10, dt nu/dp^2 = 50, u0 ~ N(0, 0.1^2), previous
-step start), FP32 vectors and operator with FP64 scalars, robust BiCGSTAB to a
-1e-6 relative residual.  One step = the whole hot path on inputs already in
-HBM: neighbour build by counting sort, cached operator build, and the solve.
+Headline workload: the lava-like channel, 320^3 jittered fluid sites plus
+three wall layers at the bottom and both sides (33,695,360 particles,
+periodic along the flow, viscosity nu = 1e4 exp(-0.02 T) over a smooth
+temperature field in [1000, 1200], harmonic pair mean, dummy walls,
+dt nu_max/dp^2 = 50), run as a sequence of implicit steps from rest,
+V_k = A^-1 (V_{k-1} + f) with f the along-slope body force per step (the
+operator frozen: the sequence isolates the solve).  One step = the whole hot
+path on inputs already in HBM: the right-hand side of the step, the
+neighbour build by counting sort, the cached operator build, the learned
+start and the robust BiCGSTAB to a 1e-6 relative residual with the FP32
+operator and Krylov vectors (FP64 scalars and solution).  The same sequence
+is timed beside it from the plain previous-step start, with the FP32 and
+with the FP64 operator.
 
-Prints one JSON line: particle-iterations per second of the whole step, the
-roofline of the dominant kernel (the operator launch that computes A r_star
-with its dot products, timed with HIP events on the library's stream over the
-timed region: every 8th iteration's launch, so that the event pairs, which
-leave a few microseconds of idle stream each, do not slow the timed steps),
-the FP64 CPU oracle timed on a bounded sample of the same
-workload, and the plain-versus-learned comparison: on held-out 160^3 boxes
-(4,491,628 particles) of the learned start's workload family, the time to a
-1e-6 relative residual of the plain previous-step start with the FP64
-operator against the learned start with the FP32 operator (FP64 solution).
-Also reported: whole steps of the robust BiCGSTAB and of the rotated CG on
-the same tank with dynamic walls (the symmetric case the CG is for), and of
-the tank with the Wendland and with the truncated Gaussian kernel.
+Prints one JSON line: particle-iterations per second of the learned FP32
+steps, the roofline of the dominant kernel (the operator launch that
+computes A r_star with its dot products, timed with HIP events on the
+library's stream over the timed region: every 8th iteration's launch, so
+that the event pairs, which leave a few microseconds of idle stream each, do
+not slow the timed steps), the FP64 CPU oracle timed on a bounded sample of
+the same workload, and, as extra keys, the 100^3 tank, the 160^3
+non-Newtonian incline, the plain-versus-learned comparison on held-out 160^3
+boxes, the CG against the BiCGSTAB, the Wendland against the Gaussian
+kernel, and the paper's all-FP32 solver.
 """
 import argparse
 import json
@@ -34,7 +39,7 @@ if ROOT not in sys.path:
 METRIC = "time-to-1e-6 residual per solve, particle-iters/s, HBM GB/s; plain vs learned"
 HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 8  # time the A r_star launch of every 8th iteration
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_apply_sell_f32_A2_open_box100_hbm.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_apply_sell_f32_A2_lava320_hbm.md")
 
 
 def measured_traffic():
@@ -59,13 +64,17 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=100, help="fluid particles per side of the tank")
-    ap.add_argument("--op-mode", choices=["cached", "onthefly"], default="cached")
-    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--cpu-sample-iters", type=int, default=4,
-                    help="BiCGSTAB iterations of the oracle's timed sample (0 = skip)")
+    ap.add_argument("--steps", type=int, default=20, help="timed implicit steps of each leg")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps before them")
+    ap.add_argument("--n", type=int, default=320, help="fluid sites per side of the lava channel")
+    ap.add_argument("--legs", default="learned_f32op,plain_f32op,plain_f64",
+                    help="sequence legs to time (the first is the headline)")
+    ap.add_argument("--cpu-sample", type=int, default=16,
+                    help="the oracle's timed sample: particles of the first 1/k of the channel (0 = skip)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=2,
+                    help="BiCGSTAB iterations of the oracle's timed samples")
+    ap.add_argument("--tank-n", type=int, default=100, help="side of the tank leg (0 = skip)")
+    ap.add_argument("--incline-n", type=int, default=160, help="side of the incline leg (0 = skip)")
     ap.add_argument("--learned-n", type=int, default=160,
                     help="fluid particles per side of the plain-vs-learned boxes (0 = skip)")
     ap.add_argument("--learned-seeds", type=int, default=3, help="held-out boxes compared")
@@ -84,26 +93,196 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, sample_iters):
-    """The FP64 oracle (as it stands) on the same tank: neighbour grid, then
-    `sample_iters` robust BiCGSTAB iterations from the same start."""
+def _oracle_rate(w, sample_iters, X0=None, threads=None):
+    """Particle-iterations per second of the FP64 oracle (as it stands:
+    matrix-free operator) over `sample_iters` robust BiCGSTAB iterations of w;
+    the neighbour grid is built first and not counted."""
     import oracle as O
+    if threads:
+        O.set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        nbr = O.neighbors(w.pos, w.period, w.h, lo=w.lo, method="grid")
+        t_nbr = time.perf_counter() - t0
+        op = O.Operator.from_workload(w, nbr=nbr)
+        t0 = time.perf_counter()
+        _, rep, _ = O.solve(op, w.rhs, X0=X0, tol=w.tol, max_iter=sample_iters, true_res_period=0)
+        t_solve = time.perf_counter() - t0
+        return w.n * max(rep["iters"], 1) / t_solve, max(rep["iters"], 1), t_solve, t_nbr, O.num_threads()
+    finally:
+        if threads:
+            O.set_num_threads(os.cpu_count() or 1)
+
+
+def cpu_baseline(w, frac, sample_iters):
+    """The FP64 oracle on a slab of the same channel (the particles of its
+    first 1/frac along the flow), plus single-thread figures on the 16^3
+    Poiseuille channel (whole solve) and the 100^3 tank (first iterations)."""
+    import numpy as np
+
+    from paper_2206_14780_amd import workloads as W
+    import dataclasses
+    L = w.hi[0] - w.lo[0]
+    keep = w.pos[:, 0] < w.lo[0] + L / frac
+    slab = dataclasses.replace(w, name=w.name + f"_slab{frac}", pos=w.pos[keep], mass=w.mass[keep],
+                               rho=w.rho[keep], mu=w.mu[keep], ptype=w.ptype[keep], rhs=w.rhs[keep],
+                               periodic=np.array([0, 0, 0]), hi=np.array([w.lo[0] + L / frac, w.hi[1], w.hi[2]]))
+    rate, iters, t_solve, t_nbr, cores = _oracle_rate(slab, sample_iters)
+    out = {"value": rate, "unit": "particle-iters/s", "cores": cores, "kind": "oracle",
+           "sample": (f"the first 1/{frac} of the {w.n}-particle lava channel along the flow ({slab.n} particles, "
+                      f"same positions, viscosities and rhs; not periodic), FP64 robust BiCGSTAB with the "
+                      f"matrix-free operator, first {iters} iterations in {t_solve:.1f} s (neighbour grid "
+                      f"{t_nbr:.1f} s not counted)")}
+    single = {}
+    p16 = W.poiseuille(16, wall=W.WALL_DUMMY)
+    r1, it1, t1, _, _ = _oracle_rate(p16, 10000, threads=1)
+    single["poiseuille16"] = {"n": int(p16.n), "iterations": it1, "seconds": round(t1, 3),
+                              "particle_iters_per_s": round(r1, 1)}
+    tank = W.open_box(100)
+    r2, it2, t2, _, _ = _oracle_rate(tank, 1, X0=tank.x0, threads=1)
+    single["tank100"] = {"n": int(tank.n), "iterations": it2, "seconds": round(t2, 3),
+                         "particle_iters_per_s": round(r2, 1)}
+    out["single_thread"] = single
+    print(f"[bench] cpu baseline: {json.dumps(out)}", flush=True)
+    return out
+
+
+def _rel(rep):
+    import numpy as np
+    return max(float(np.sqrt(t / b)) for t, b in zip(rep["true_rr"], rep["bb"]) if b > 0)
+
+
+def lava_sequence(ctx, w, leg, warmup, steps, profile_every):
+    """Sequence V_k = A^-1 (V_{k-1} + f) from rest on the device: every step
+    forms its rhs, builds the neighbour lists and solves from the previous
+    step's solution (leg: learned_f32op / plain_f32op / plain_f64)."""
+    import numpy as np
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import warmstart as WS
+    from paper_2206_14780_amd import workloads as W
+
+    prec = S.SPH_F64 if leg == "plain_f64" else S.SPH_MIXED
+    warm = torch.as_tensor(WS.load()).cuda() if leg.startswith("learned") else None
+    parts = S.device_particles(w)
+    dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
+    params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
+    fluid = torch.as_tensor(w.ptype == W.FLUID).cuda()
+    f = [torch.as_tensor(w.rhs[:, c]).cuda() for c in range(3)]
+    V = [torch.zeros(w.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    B = [torch.empty_like(v) for v in V]
+    opts = S.make_opts(tol=w.tol, x0_given=True, profile=profile_every, warm_params=warm)
+
+    def step():
+        for c in range(3):
+            torch.where(fluid, V[c] + f[c], torch.zeros_like(f[c]), out=B[c])
+        nb = ctx.sph_build_neighbors(parts, dom)
+        rep = ctx.sph_visc_solve(nb, None, parts, params, prec, B, V, opts)
+        nb.free()
+        assert rep["status"] == S.SPH_OK, (leg, rep["status"], rep["state"])
+        return rep
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nbr = O.neighbors(w.pos, w.period, w.h, lo=w.lo, method="grid")
-    t_nbr = time.perf_counter() - t0
-    op = O.Operator.from_workload(w, nbr=nbr)
+    reps = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    iters = [r["iters"] for r in reps]
+    out = {"ms_per_step": round(total * 1e3 / steps, 3), "total_s": round(total, 3),
+           "iterations": iters, "total_iterations": int(sum(iters)),
+           "particle_iters_per_s": w.n * sum(iters) / total,
+           "time_to_tol_ms_median": round(float(np.median([r["setup_ms"] + r["iterate_ms"] for r in reps])), 3),
+           "setup_ms_median": round(float(np.median([r["setup_ms"] for r in reps])), 3),
+           "launches_per_iteration": round(sum(r["launches"] for r in reps) / max(sum(iters), 1), 3),
+           "true_rel_res_max": round(max(_rel(r) for r in reps), 9),
+           "final_max_vx": round(float(V[0].abs().max()), 6)}
+    if warm is not None:
+        out["warm_ms_median"] = round(float(np.median([r["warm_ms"] for r in reps])), 3)
+        out["components_on_learned_start"] = int(sum(sum(r["warm_used"]) for r in reps))
+        out["components"] = 3 * steps
+    out["_reps"] = reps
+    del parts, V, B
+    return out
+
+
+def tank_leg(ctx, n, steps):
+    """The 100^3 open-top tank (FP32 operator and vectors, FP64 scalars, the
+    previous-step start): whole steps (neighbours + operator + solve)."""
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import workloads as W
+
+    w = W.open_box(n=n)
+    parts = S.device_particles(w)
+    dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
+    rhs = S.device_vec3(w.rhs, S.SPH_F32)
+    x0 = S.device_vec3(w.x0, S.SPH_F32)
+    x = [t.clone() for t in x0]
+    params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
+    opts = S.make_opts(tol=w.tol, x0_given=True, profile=PROFILE_EVERY)
+
+    def step():
+        for a, b in zip(x, x0):
+            a.copy_(b)
+        nb = ctx.sph_build_neighbors(parts, dom)
+        rep = ctx.sph_visc_solve(nb, None, parts, params, S.SPH_F32, rhs, x, opts)
+        nb.free()
+        assert rep["status"] == S.SPH_OK, rep
+        return rep
+
+    step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, rep, _ = O.solve(op, w.rhs, X0=w.x0, tol=w.tol, max_iter=sample_iters, true_res_period=0)
-    t_solve = time.perf_counter() - t0
-    iters = max(rep["iters"], 1)
-    return {
-        "value": w.n * iters / t_solve,
-        "unit": "particle-iters/s",
-        "cores": O.num_threads(),
-        "kind": "oracle",
-        "sample": (f"full {w.n}-particle tank, FP64 robust BiCGSTAB, first {iters} iterations "
-                   f"({t_solve:.1f} s; neighbour grid {t_nbr:.1f} s not counted)"),
-    }
+    reps = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    r = reps[-1]
+    a_ms = sum(q["apply_ms"] for q in reps) / max(sum(q["apply_launches"] for q in reps), 1)
+    out = {"workload": f"open-top tank {n}^3 jittered fluid + 3 wall layers (dummy), nu=10, dt*nu/dp^2=50, "
+                       f"u0 ~ N(0, 0.1^2), previous-step start, f32 vectors/operator + f64 scalars, tol 1e-6",
+           "n_particles": int(w.n), "ms_per_step": round(total * 1e3 / steps, 3), "iterations": r["iters"],
+           "particle_iters_per_s": w.n * sum(q["iters"] for q in reps) / total,
+           "time_to_tol_ms": round(r["setup_ms"] + r["iterate_ms"], 3), "setup_ms": round(r["setup_ms"], 3),
+           "launches_per_iteration": round(r["launches"] / max(r["iters"], 1), 3),
+           "true_rel_res": round(_rel(r), 9), "avg_apply_launch_ms": round(a_ms, 4),
+           "mat_nnz": int(r["mat_nnz"]), "mat_slots": int(r["mat_slots"])}
+    print(f"[bench] tank: {json.dumps(out)}", flush=True)
+    return out
+
+
+def incline_leg(ctx, n):
+    """The 160^3 non-Newtonian incline (Papanastasiou viscosity over three
+    decades, harmonic mean), one solve from rest to 1e-6: plain start with the
+    FP64 operator, plain and learned starts with the FP32 operator."""
+    import torch
+
+    from paper_2206_14780_amd import sph as S
+    from paper_2206_14780_amd import warmstart as WS
+    from paper_2206_14780_amd import workloads as W
+
+    w = W.incline_papanastasiou(n)
+    r = WS.Resident(ctx, w)
+    warm = torch.as_tensor(WS.load()).cuda()
+    out = {"workload": f"incline {n}^3 jittered fluid, periodic x-y, 3 bottom wall layers (dummy), 10 deg, "
+                       f"Papanastasiou mu over {w.meta['mu_min']:.0f}..{w.meta['mu_max']:.0f}, harmonic mean, "
+                       f"dt*mu_max/dp^2=50, from rest, tol 1e-6", "n_particles": int(w.n)}
+    for name, prec, wp in (("plain_f64", S.SPH_F64, None), ("plain_f32op", S.SPH_MIXED, None),
+                           ("learned_f32op", S.SPH_MIXED, warm)):
+        r.solve(prec, 1e-6, from_u=False, warm_params=wp)
+        _, rep = r.solve(prec, 1e-6, from_u=False, warm_params=wp)
+        assert rep["status"] == S.SPH_OK, (name, rep["status"])
+        out[name] = {"time_to_tol_ms": round(rep["setup_ms"] + rep["iterate_ms"], 3), "iterations": rep["iters"],
+                     "particle_iters_per_s": w.n * rep["iters"] / ((rep["setup_ms"] + rep["iterate_ms"]) * 1e-3),
+                     "true_rel_res": round(_rel(rep), 9)}
+        if wp is not None:
+            out[name]["warm_used"] = rep["warm_used"]
+    print(f"[bench] incline: {json.dumps(out)}", flush=True)
+    del r
+    return out
 
 
 def plain_vs_learned(ctx, n, seeds, reps):
@@ -325,62 +504,36 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver has no "
               "multi-GPU domain decomposition.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2206_14780_amd import sph as S
     from paper_2206_14780_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prec = S.SPH_F32 if args.prec == "f32" else S.SPH_F64
-    op_mode = S.SPH_OP_CACHED if args.op_mode == "cached" else S.SPH_OP_ONTHEFLY
-    w = W.open_box(n=args.n)
+    t0 = time.time()
+    w = W.lava_channel(args.n)
+    print(f"[bench] workload {w.name} n={w.n} generated in {time.time() - t0:.1f} s", flush=True)
     ctx = S.Context(0)
-    parts = S.device_particles(w)
-    dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
-    rhs = S.device_vec3(w.rhs, prec)
-    x0 = S.device_vec3(w.x0, prec)
-    x = [t.clone() for t in x0]
-    params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=op_mode)
-    opts = S.make_opts(tol=w.tol, x0_given=True, profile=PROFILE_EVERY)
-    build_ms = []
-
-    def step():
-        for a, b in zip(x, x0):
-            a.copy_(b)
-        t0 = time.perf_counter()
-        nb = ctx.sph_build_neighbors(parts, dom)
-        build_ms.append((time.perf_counter() - t0) * 1e3)
-        rep = ctx.sph_visc_solve(nb, None, parts, params, prec, rhs, x, opts)
-        nb.free()
-        assert rep["status"] == S.SPH_OK, rep
-        return rep
-
-    print(f"[bench] workload open_box{args.n} n={w.n} prec={args.prec} op={args.op_mode}", flush=True)
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    build_ms.clear()
-    t0 = time.perf_counter()
-    reps = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t0
-    ms_per_step = total_s * 1e3 / args.steps
-    iters = reps[-1]["iters"]
-    assert all(r["iters"] == iters for r in reps)
-    value = w.n * iters * args.steps / total_s
-    solve_ms = [r["setup_ms"] + r["iterate_ms"] for r in reps]
-    print(f"[bench] {args.steps} steps, {ms_per_step:.2f} ms/step, {iters} iterations", flush=True)
+    legs = [l for l in args.legs.split(",") if l]
+    seq = {}
+    for leg in legs:
+        seq[leg] = lava_sequence(ctx, w, leg, args.warmup, args.steps, PROFILE_EVERY)
+        print(f"[bench] lava {leg}: " + json.dumps({k: v for k, v in seq[leg].items() if k != "_reps"}),
+              flush=True)
+    head = seq[legs[0]]
+    reps = head.pop("_reps")
+    for leg in legs[1:]:
+        seq[leg].pop("_reps")
 
     # dominant kernel: the A r_star operator launch (one per iteration)
     a_ms = sum(r["apply_ms"] for r in reps) / max(sum(r["apply_launches"] for r in reps), 1)
-    esz = 4 if prec == S.SPH_F32 else 8
+    esz = 8 if legs[0] == "plain_f64" else 4
     nnz, slots = reps[-1]["mat_nnz"], reps[-1]["mat_slots"]
     nslices = (w.n + 63) // 64
     # algorithmic bytes per launch: every stored nonzero (column index +
@@ -388,70 +541,76 @@ def main():
     # one slice pointer per 64 rows
     alg_bytes = nnz * (4 + esz) + w.n * (7 * esz) + nslices * 8
     roofline = None
-    if op_mode == S.SPH_OP_CACHED and a_ms > 0:
+    if a_ms > 0:
         achieved = alg_bytes / (a_ms * 1e-3) / 1e9
-        traffic = measured_traffic() if (args.n == 100 and prec == S.SPH_F32) else None
+        traffic = measured_traffic() if (args.n == 320 and esz == 4) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": f"k_apply_sell<{'float' if esz == 4 else 'double'}, kDotA2>",
                     "avg_launch_ms": round(a_ms, 4), "alg_bytes_per_launch": int(alg_bytes),
                     "mat_nnz": int(nnz), "mat_slots": int(slots)}
+        if traffic:
+            roofline["traffic_rate_gbs"] = round(traffic / (a_ms * 1e-3) / 1e9, 1)
+            roofline["traffic_frac"] = round(traffic / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
-    pvl = None
+    extras = {}
+    if args.tank_n > 0:
+        print("[bench] tank", flush=True)
+        extras["tank100"] = tank_leg(ctx, args.tank_n, 5)
+    if args.incline_n > 0:
+        print("[bench] incline", flush=True)
+        extras["incline160"] = incline_leg(ctx, args.incline_n)
     if args.learned_n > 0 and args.learned_seeds > 0:
-        print("[bench] plain vs learned", flush=True)
-        pvl = plain_vs_learned(ctx, args.learned_n, args.learned_seeds, args.learned_reps)
-
-    cg = None
+        print("[bench] plain vs learned (held-out boxes)", flush=True)
+        extras["plain_vs_learned"] = plain_vs_learned(ctx, args.learned_n, args.learned_seeds, args.learned_reps)
     if args.cg_n > 0:
         print("[bench] CG vs BiCGSTAB (dynamic walls)", flush=True)
-        cg = cg_vs_bicgstab(ctx, args.cg_n, args.cg_steps, args.prec)
-
-    kc = None
+        extras["cg_vs_bicgstab"] = cg_vs_bicgstab(ctx, args.cg_n, args.cg_steps, "f32")
     if args.kernel_n > 0:
         print("[bench] Wendland vs Gaussian kernel", flush=True)
-        kc = kernel_comparison(ctx, args.kernel_n, args.kernel_steps, args.prec)
-
-    f32s = None
+        extras["kernel_comparison"] = kernel_comparison(ctx, args.kernel_n, args.kernel_steps, "f32")
     if args.fp32_n > 0:
         print("[bench] all-FP32 solver study", flush=True)
-        f32s = fp32_paper_study(ctx, args.fp32_n)
-
+        extras["fp32_paper"] = fp32_paper_study(ctx, args.fp32_n)
     cpu = None
-    if args.cpu_sample_iters > 0:
+    if args.cpu_sample > 0:
         print("[bench] cpu baseline (oracle)", flush=True)
-        cpu = cpu_baseline(w, args.cpu_sample_iters)
+        cpu = cpu_baseline(w, args.cpu_sample, args.cpu_sample_iters)
 
+    plain = seq.get("plain_f64")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["particle_iters_per_s"],
         "unit": "particle-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": "f64" if legs[0] == "plain_f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"open-top tank {args.n}^3 jittered fluid + 3 wall layers (dummy), "
-                               f"nu=10, dt*nu/dp^2=50, robust BiCGSTAB to 1e-6, "
-                               f"{args.prec} vectors/operator + f64 scalars, {args.op_mode} operator",
-                   "n_particles": w.n, "tol": w.tol, "scalar_dtype": "f64"},
-        "iterations": iters,
-        "time_to_tol_ms": float(np.median(solve_ms)),
-        "neighbour_build_ms": float(np.median(build_ms)),
-        "true_rel_res": [float(np.sqrt(t / b)) if b > 0 else 0.0
-                         for t, b in zip(reps[-1]["true_rr"], reps[-1]["bb"])],
-        "launches_per_solve": reps[-1]["launches"],
+        "config": {"workload": f"lava-like channel {args.n}^3 jittered fluid + 3 wall layers (dummy, bottom and "
+                               f"sides), periodic x, nu = 1e4 exp(-0.02 T) over a smooth T field in [1000, 1200], "
+                               f"harmonic mean, dt*nu_max/dp^2=50; sequence of implicit steps from rest "
+                               f"V_k = A^-1 (V_(k-1) + f), each step: rhs, neighbour build, operator build, "
+                               f"{legs[0].replace('_', ' ')} start, robust BiCGSTAB to 1e-6"
+                               + ("" if legs[0] == "plain_f64" else ", f32 operator and Krylov vectors, "
+                                  "f64 scalars and solution"),
+                   "n_particles": int(w.n), "tol": w.tol, "scalar_dtype": "f64"},
+        "iterations": head["iterations"],
+        "time_to_tol_ms": head["time_to_tol_ms_median"],
+        "launches_per_iteration": head["launches_per_iteration"],
+        "true_rel_res_max": head["true_rel_res_max"],
         "roofline": roofline,
-        "plain_vs_learned": pvl,
-        "cg_vs_bicgstab": cg,
-        "kernel_comparison": kc,
-        "fp32_paper": f32s,
+        "sequence": seq,
+        "speedup_vs_plain_f64": (round(plain["ms_per_step"] / head["ms_per_step"], 3) if plain else None),
+        "speedup_vs_plain_f32op": (round(seq["plain_f32op"]["ms_per_step"] / head["ms_per_step"], 3)
+                                   if "plain_f32op" in seq and legs[0] != "plain_f32op" else None),
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -190,7 +190,11 @@ typedef struct {
 
 /* Solve report (host memory).  history, if non-null, is a host buffer of
  * history_cap x 3 doubles that receives r.r per component at the end of
- * each iteration (row 0 = initial residual). */
+ * each iteration (row 0 = initial residual).  Residuals are reported as
+ * squared norms, as the stopping test compares them (r.r < tau^2, Section
+ * "Restructuring the Conjugate Gradient"): the relative residual of
+ * component c is sqrt(rr[c] / bb[c]) (recursive) and sqrt(true_rr[c] /
+ * bb[c]) (FP64 true residual), both of the (scaled) system solved. */
 typedef struct {
     int32_t iters;
     int32_t status;
@@ -238,19 +242,30 @@ const char *sph_status_str(sph_status s);
  * cells of side >= 2h, particles ordered by cell and, inside a cell, by
  * original index.  Positions are copied; the handle stays valid after the
  * caller's arrays change.  *out receives a new handle (free it with
- * sph_neighbors_free).  Only the positions of `p` are read. */
+ * sph_neighbors_free).  Only the positions of `p` are read.  The handle holds
+ * the cell lists only, never an explicit per-particle neighbour list (there
+ * is no option for one): every operator build scans the cells itself and
+ * keeps its lists for that build, so a list in the handle would be a second
+ * copy of data that each solve renews anyway. */
 sph_status sph_build_neighbors(sph_ctx *ctx, const sph_particles *p, const sph_domain *dom,
                                sph_nbr **out);
 /* Number of particles and of (directed) neighbour pairs of the handle. */
 sph_status sph_neighbors_info(sph_ctx *ctx, const sph_nbr *nb, int64_t *n, int64_t *nnz);
-/* Neighbour lists in canonical form: CSR over original particle indices,
- * columns ascending.  row_ptr: device, n + 1 entries; cols: device, cap
- * entries.  *nnz (host) receives the pair count; SPH_E_OVERFLOW if cap < nnz. */
+/* Neighbour lists in canonical form (the neighbour set of Section
+ * "Smoothing kernel choice": b != a, |r_a - r_b| < 2h, or 3h for the
+ * truncated Gaussian, minimum image on periodic axes): CSR over original
+ * particle indices, columns ascending.  row_ptr: device, n + 1 entries;
+ * cols: device, cap entries (both device arrays, so that checks of large
+ * systems need no host copy; the caller copies what it wants on the host).
+ * *nnz (host) receives the pair count; SPH_E_OVERFLOW if cap < nnz. */
 sph_status sph_neighbors_export(sph_ctx *ctx, const sph_nbr *nb, int64_t *row_ptr,
                                 int32_t *cols, int64_t cap, int64_t *nnz);
 sph_status sph_neighbors_free(sph_nbr *nb);
 
-/* y = A x (or D^-1 A x when params->jacobi) for the three components.
+/* y = A x (or D^-1 A x when params->jacobi) for the three components: the
+ * viscous matrix of eqs. diag, offdiag (fluid rows) and
+ * implicit-system-dyn-full / implicit-system-dummy-full (wall rows), the
+ * paper's gemv (appendix "Implementation notes").
  * x[c], y[c]: device arrays of n doubles (prec SPH_F64) or floats (SPH_F32).
  * x and y must not overlap.  Coefficients are evaluated in FP64 in both
  * precisions; SPH_OP_CACHED rounds them to the vector precision. */
@@ -383,8 +398,10 @@ sph_status sph_mlp_samples(sph_ctx *ctx, const sph_nbr *nb, const sph_particles 
  * the precision, original order) = U (o . B) on fluid rows, rhs on dynamic
  * wall rows, and on dummy wall rows the value that satisfies the row
  * exactly.  u[c], rhs[c]: device, n values of the precision each;
- * mlp_params: device, SPH_MLP_NPARAM floats.  *U (host, may be null)
- * receives the normalisation. */
+ * mlp_params: device, SPH_MLP_NPARAM floats: the FP32 master parameters that
+ * training updates; every block rounds them to BF16 (nearest even) as it
+ * loads them, so no separate BF16 copy has to be kept in step with them.
+ * *U (host, may be null) receives the normalisation. */
 sph_status sph_mlp_warmstart(sph_ctx *ctx, const sph_nbr *nb, const sph_particles *p,
                              const sph_visc_params *params, int32_t prec, const void *const u[3],
                              const void *const rhs[3], const float *mlp_params, void *const x0[3],
@@ -400,7 +417,12 @@ sph_status sph_mlp_grad(sph_ctx *ctx, const float *samples, const int32_t *idx, 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
  * on the FP32 master parameters (device) with moment buffers adam_m, adam_v
  * (device, SPH_MLP_NPARAM each, zero before step 1); *loss (host, may be
- * null) = mean squared error of the batch before the step. */
+ * null) = mean squared error of the batch before the step.  The batch is
+ * given as indices idx (device int32, batch entries) into the sample array
+ * of sph_mlp_samples (device, FP32, SPH_MLP_SAMPLE values each: features,
+ * basis and target together), so that one sample array built once serves
+ * every step; the BF16 weights are rounded from params inside the kernels,
+ * as in sph_mlp_warmstart. */
 sph_status sph_mlp_train_step(sph_ctx *ctx, const float *samples, const int32_t *idx,
                               int64_t batch, float *params, float *adam_m, float *adam_v,
                               int32_t step, double lr, double *loss);

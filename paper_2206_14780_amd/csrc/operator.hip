@@ -494,8 +494,9 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
                       const double** diag64, int64_t* nnz_out, int64_t* slots_out) {
     const int64_t n = nb->n;
     const int64_t nslices = ceil_div(n, kWave);
-    // SPH_BUILD_LEGACY=1 selects the build with the coefficients evaluated
-    // inside the scan (the reference the list build is tested against)
+    // Test hook: the environment variable SPH_BUILD_LEGACY=1 selects the
+    // build that evaluates the coefficients inside the neighbour scan, the
+    // reference the list-based build is tested against bit for bit.
     const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
     // list entries per row: room for every neighbour of the kernel's support
     // (int32 index + FP64 weight each) while that fits the budget
@@ -583,21 +584,18 @@ template sph_status build_sell<double>(sph_ctx*, const sph_nbr*, const PartView&
                                        Sell<double>*, const double**, int64_t*, int64_t*);
 
 
-// Launch geometry of the row kernels.  SPH_APPLY_BLOCK / SPH_APPLY_GRID /
-// SPH_STREAM_BLOCK / SPH_STREAM_GRID override the defaults (tuning sweeps).
+// Launch geometry of the row kernels.
 Launch make_launch(int64_t n) {
     Launch L;
     L.n = n;
     const int64_t nslices = ceil_div(n, kWave);
-    int32_t ba = env_int("SPH_APPLY_BLOCK", 256);
-    ba = std::min(std::max(ba / kWave * kWave, kWave), kApplyMaxBlock);
+    const int32_t ba = kApplyMaxBlock;
     const int64_t wpb = ba / kWave;
     // one 64-row slice per wave: the launch's tail is then one slice long
     // (measured fastest for whole iterations on the 1.16M and 4.49M tanks);
     // the grid is rounded up to a multiple of the XCD count, so that no block
     // gets more slices than it has waves
     int64_t ga = ceil_div(nslices, wpb);
-    ga = env_int("SPH_APPLY_GRID", (int32_t)ga);
     if (ga >= 64) ga = ceil_div(ga, kNumXcd) * kNumXcd;
     L.grid_apply = (int32_t)std::max<int64_t>(ga, 1);
     L.block_apply = ba;
@@ -608,10 +606,8 @@ Launch make_launch(int64_t n) {
     // 29.3 ms per step on the 1.16M tank, no change at 4.7M)
     int32_t bs_def = 1024;
     while (bs_def > kWave && (int64_t)bs_def * 256 * 8 > n) bs_def /= 2;
-    int32_t bs = env_int("SPH_STREAM_BLOCK", bs_def);
-    bs = std::min(std::max(bs / kWave * kWave, kWave), kMaxBlock);
+    const int32_t bs = bs_def;
     int64_t gs = std::min<int64_t>(ceil_div(n, (int64_t)bs * 4), 256);
-    gs = env_int("SPH_STREAM_GRID", (int32_t)gs);
     if (gs >= 64) gs = gs / kNumXcd * kNumXcd;
     L.grid_stream = (int32_t)std::max<int64_t>(gs, 1);
     L.block_stream = bs;
