@@ -369,12 +369,14 @@ sph_status sph_semi_implicit_step(sph_ctx *ctx, const sph_domain *dom, const sph
  * "Implementation notes"): a per-particle MLP
  *   x[4] -> 64 -> 64 -> 64 -> o[3] (ReLU), pred = o . B,
  * one sample per fluid particle and velocity component, with
- *   features x = (u_c / U, d_c / U, log10 nu, log10(dt nu / h^2)),
+ *   features x = (u_c / U, d_c / U, log10 nu - L, log10(dt nu / h^2)),
  *   basis    B = (b_c / U, u_c / U, d_c / U),  target t = V_c / U,
  * d = D^-1 (u - A u) (the viscous increment of u scaled by the row's
  * diagonal D = A_rr: one Jacobi correction), A the unscaled matrix of
  * sph_visc_params, u the current velocity, b the right-hand side,
- * nu = mu / rho, U the RMS of b over fluid rows and components.  The initial guess is x0_c = U pred on fluid rows; wall rows
+ * nu = mu / rho, L the mean of log10 nu over fluid rows (the viscosity
+ * feature is relative to the geometric-mean viscosity: scale-free), U the
+ * RMS of b over fluid rows and components.  The initial guess is x0_c = U pred on fluid rows; wall rows
  * take b (dynamic model) or satisfy their own row exactly, x0_w = b_w -
  * sum_a W x0_a / sum_a W (dummy model).
  * Parameters: one FP32 vector of SPH_MLP_NPARAM values (W1 [4][64], b1,

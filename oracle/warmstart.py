@@ -15,7 +15,10 @@ particle k and velocity component c:
                                    one Jacobi correction, of the size of u
                                    however stiff the row is)
   U     = RMS of b over fluid rows and components (1 if that is 0)
-  x     = (u_c / U, d_c / U, log10 nu_k, log10(dt nu_k / h^2)), nu = mu / rho
+  L     = mean of log10 nu over fluid rows (nu = mu / rho)
+  x     = (u_c / U, d_c / U, log10 nu_k - L, log10(dt nu_k / h^2)): the
+          viscosity relative to the system's geometric mean (unchanged when
+          every viscosity is scaled), its magnitude through the stiffness
   B     = (b_c / U, u_c / U, d_c / U)
   t     = V_c / U                 (V the converged solution, training only)
   x0_c  = U * (o . B)             with o = MLP(x)
@@ -59,7 +62,8 @@ def samples(op: Operator, u, b, mu, rho, ptype, target=None):
     S = np.zeros((n, 3, 8))
     S[:, :, 0] = u / U
     S[:, :, 1] = d / U
-    S[:, :, 2] = np.log10(nu)[:, None]
+    L = float(np.mean(np.log10(nu[fl]))) if nfl else 0.0
+    S[:, :, 2] = (np.log10(nu) - L)[:, None]
     S[:, :, 3] = np.log10(op.dt * nu / (op.h * op.h))[:, None]
     S[:, :, 4] = b / U
     S[:, :, 5] = u / U

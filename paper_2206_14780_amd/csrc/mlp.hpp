@@ -32,6 +32,7 @@ constexpr int kWiRrL = 0;    // [3] true r.r of the learned guess
 constexpr int kWiRrP = 3;    // [3] true r.r of the plain start
 constexpr int kWiUse = 6;    // [3] 1.0 where the learned guess is kept
 constexpr int kWiU = 9;      // U
+constexpr int kWiLogNu = 10; // mean of log10 nu over fluid rows
 constexpr int kWiSize = 16;
 
 // Operator data the learned start needs (cell order).

@@ -7,9 +7,12 @@
 // One sample per fluid row r and component c (wall rows: all zero):
 //   d = (u - A u) / A_rr = -(1/A_rr) sum_k A_rk (u_k - u_r)   (one Jacobi
 //       correction of u: the viscous increment scaled by the row's diagonal)
-//   x = (u_c / U, d_c / U, log10 nu_r, log10(dt nu_r / h^2)),  nu = mu / rho
+//   x = (u_c / U, d_c / U, log10 nu_r - L, log10(dt nu_r / h^2)),  nu = mu / rho
 //   B = (b_c / U, u_c / U, d_c / U),  t = V_c / U (training only)
-// with U the RMS of b over fluid rows and components (1 if that is 0).
+// with U the RMS of b over fluid rows and components (1 if that is 0) and L
+// the mean of log10 nu over fluid rows: the viscosity enters relative to the
+// system's geometric-mean viscosity (scale-free), its magnitude through the
+// stiffness dt nu / h^2.
 #include <algorithm>
 #include <cmath>
 
@@ -32,43 +35,47 @@ struct Rhs {
     __device__ double at(int64_t r, int c) const { return (double)b[c][perm[r]]; }
 };
 
-// Partial sums of b.b over fluid rows and of the fluid row count, in the
-// caller's order (b read contiguously; the type through iperm).
+// Partial sums over fluid rows of b.b, of the row count and of log10 nu, in
+// the caller's order (b read contiguously; type, mu and rho through iperm).
 template <typename C>
 __global__ __launch_bounds__(kBlock) void k_warm_stats(int64_t n, Rhs<C> rhs, const int32_t* __restrict__ iperm,
-                                                       const uint8_t* __restrict__ type, double* __restrict__ part) {
-    __shared__ double lds[2 * kMaxWaves];
-    double acc[2] = {0.0, 0.0};
+                                                       PartView pv, double* __restrict__ part) {
+    __shared__ double lds[3 * kMaxWaves];
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (type[iperm[i]] != SPH_FLUID) continue;
+        const int32_t r = iperm[i];
+        if (pv.type[r] != SPH_FLUID) continue;
         for (int c = 0; c < 3; ++c) {
             const double v = (double)rhs.b[c][i];
             acc[0] += v * v;
         }
         acc[1] += 1.0;
+        acc[2] += log10(pv.mu[r] / pv.rho[r]);
     }
-    write_partials<2>(acc, lds, part);
+    write_partials<3>(acc, lds, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_warm_scale(const double* __restrict__ part, int nblk,
                                                        double* __restrict__ info) {
-    __shared__ double lds[2 * kMaxWaves];
-    double s[2];
-    reduce_partials<2>(part, nblk, s, lds);
+    __shared__ double lds[3 * kMaxWaves];
+    double s[3];
+    reduce_partials<3>(part, nblk, s, lds);
     if (threadIdx.x == 0) {
         double U = s[1] > 0.0 ? sqrt(s[0] / (3.0 * s[1])) : 0.0;
         if (!(U > 0.0) || !finite_d(U)) U = 1.0;
         info[kWiU] = U;
+        const double L = s[1] > 0.0 ? s[2] / s[1] : 0.0;
+        info[kWiLogNu] = finite_d(L) ? L : 0.0;
     }
 }
 
 // Writes the 3 samples of row r given d.
 template <typename C>
 __device__ inline void warm_write(int64_t r, const Rhs<C>& rhs, const V3<C>& u, const double (&d)[3],
-                                  const PartView& pv, double dt, double h, double U,
+                                  const PartView& pv, double dt, double h, double U, double lognu_mean,
                                   const double* const* tgt, float* __restrict__ out) {
     const double nu = pv.mu[r] / pv.rho[r];
-    const float f2 = (float)log10(nu);
+    const float f2 = (float)(log10(nu) - lognu_mean);
     const float f3 = (float)log10(dt * nu / (h * h));
     const double uu[3] = {(double)u.x, (double)u.y, (double)u.z};
     for (int c = 0; c < 3; ++c) {
@@ -149,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_sell(FeatArgs<T, C> a, Sel
             const double D = a.diag64[r];
             for (int c = 0; c < 3; ++c) d[c] /= D;
         }
-        warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+        warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.info[kWiLogNu],
+                      a.has_tgt ? a.tgt : nullptr, o);
     }
     if (a.rplain) write_partials<3>(acc, lds, a.part);
 }
@@ -175,7 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_warm_feat_otf(FeatArgs<T, C> a, NbrV
     });
     const double f = a.dt / a.diag64[r];
     const double d[3] = {f * s0, f * s1, f * s2};
-    warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.has_tgt ? a.tgt : nullptr, o);
+    warm_write<C>(r, a.rhs, us, d, a.pv, a.dt, a.h, a.info[kWiU], a.info[kWiLogNu], a.has_tgt ? a.tgt : nullptr,
+                  o);
 }
 
 // x = U pred on fluid rows, b on dynamic walls, 0 on dummy walls (filled next).
@@ -343,11 +352,10 @@ sph_status warm_samples(sph_ctx* ctx, const WarmOp<T>& w, const void* const rhs[
                         const PlainResidual<T>* pr) {
     const int64_t n = w.nb->n;
     double* part = nullptr;
-    SPH_TRY(ctx->ensure_t(kWarmPart, 2 * kStatBlocks, &part));
+    SPH_TRY(ctx->ensure_t(kWarmPart, 3 * kStatBlocks, &part));
     const Rhs<C> rb = make_rhs<C>(w.nb, rhs);
     const int sb = (int)std::min<int64_t>(kStatBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
-    hipLaunchKernelGGL(k_warm_stats<C>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.nb->iperm, w.pv.type,
-                       part);
+    hipLaunchKernelGGL(k_warm_stats<C>, dim3(sb), dim3(kBlock), 0, ctx->stream, n, rb, w.nb->iperm, w.pv, part);
     hipLaunchKernelGGL(k_warm_scale, dim3(1), dim3(kBlock), 0, ctx->stream, (const double*)part, sb, info);
     SPH_LAUNCHED("k_warm_stats/k_warm_scale");
     FeatArgs<T, C> a;

@@ -133,6 +133,48 @@ def generate(ctx: S.Context, make: Callable[[int], W.Workload], seeds: Iterable[
     return torch.cat(chunks), info
 
 
+def generate_sequences(ctx: S.Context, make: Callable[[int], W.Workload], seeds: Iterable[int], steps: int,
+                       tol: float = 1e-8, log: Optional[Callable[[str], None]] = print):
+    """Samples (cuda float32, fluid rows only) of implicit-step sequences from
+    rest, V_k = A^-1 (V_{k-1} + f) with f the first step's rhs on fluid rows:
+    at step k the current velocity is u = V_{k-1}, the right-hand side
+    b = V_{k-1} + f and the target the FP64 solution V_k to `tol` from the
+    previous-step start."""
+    import torch
+    chunks, info = [], []
+    for seed in seeds:
+        t0 = time.time()
+        w = make(seed)
+        parts = S.device_particles(w)
+        nb = ctx.sph_build_neighbors(parts, S.make_domain(w.lo, w.hi, w.periodic, w.h))
+        params = S.make_params(w.dt, w.wall, w.avg, True, S.SPH_OP_CACHED)
+        fluid = torch.as_tensor(w.ptype == W.FLUID).cuda()
+        f = [torch.as_tensor(w.rhs[:, c]).cuda() for c in range(3)]
+        V = [torch.zeros(w.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        fl3 = torch.as_tensor(np.repeat(w.ptype == W.FLUID, 3), device="cuda")
+        its = []
+        for k in range(steps):
+            B = [torch.where(fluid, V[c] + f[c], torch.zeros_like(f[c])) for c in range(3)]
+            X = [v.clone() for v in V]
+            o = S.make_opts(tol=tol, x0_given=True)
+            rep = ctx.sph_visc_solve(nb, None, parts, params, S.SPH_F64, B, X, o)
+            if rep["status"] != S.SPH_OK:
+                raise RuntimeError(f"training sequence {seed} step {k}: {rep['state']}")
+            out = torch.empty((3 * w.n, SAMPLE), dtype=torch.float32, device="cuda")
+            ctx.sph_mlp_samples(nb, parts, params, V, B, X, out)
+            chunks.append(out[fl3])
+            its.append(int(rep["iters"]))
+            V = X
+        rec = {k2: float(v) for k2, v in w.meta.items() if isinstance(v, (int, float))}
+        rec.update(seed=int(seed), n=int(w.n), steps=steps, iters=its)
+        info.append(rec)
+        if log:
+            log(f"sequence {seed}: n {w.n} iters {its} ({time.time() - t0:.1f} s)")
+        nb.free()
+        del parts
+    return torch.cat(chunks), info
+
+
 def train(ctx: S.Context, samples, steps: int = 6000, batch: int = 65536, lr: float = 2e-3,
           lr_min: float = 1e-5, warmup: int = 100, seed: int = 0, params0=None,
           log_every: int = 500, log: Optional[Callable[[str], None]] = print):

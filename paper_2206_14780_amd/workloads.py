@@ -272,6 +272,20 @@ def lava_channel(n=320, seed=5, nu0=1e4, b=0.02, T_lo=1000.0, T_hi=1200.0,
                     meta=dict(dp=1.0, seed=seed))
 
 
+def training_channel(n=64, seed=6000, tol=1e-8):
+    """A lava-like channel of the learned start's training set: the generator
+    of `lava_channel` at n^3 fluid sites with parameters drawn from the seed:
+    temperature span T_hi - T_lo uniform in [50, 250] (viscosity contrast
+    e^1 .. e^5 at b = 0.02) and dt nu_max / dp^2 log-uniform in [5, 200]."""
+    rng = np.random.default_rng(seed)
+    span = float(rng.uniform(50.0, 250.0))
+    stiff = float(np.exp(rng.uniform(np.log(5.0), np.log(200.0))))
+    w = lava_channel(n, seed=seed, T_lo=1000.0, T_hi=1000.0 + span, dt_numax_dp2=stiff, tol=tol)
+    w.name = f"training_channel{n}_s{seed}"
+    w.meta.update(T_span=span, dt_numax_dp2=stiff)
+    return w
+
+
 def next_step_rhs(w: Workload, V) -> np.ndarray:
     """Right-hand side of the next implicit step of a sequence started from
     rest, V_k = A^-1 (V_{k-1} + f): the previous solution plus the per-step

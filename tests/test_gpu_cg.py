@@ -140,7 +140,7 @@ def test_cg_tank_100_fp32(ctx):
     g = GpuCase(ctx, w)
     o = dict(history=False, true_res_period=20, restart_drop=-1.0)
     X, rep = g.solve(w.rhs, S.SPH_F32, X0=w.x0, variant=S.SPH_CG, **o)
-    _check_solution(g, w, w.rhs, X, rep, _rows(w, 11), "cg tank100 f32")
+    _check_solution(g, w, w.rhs, X, rep, _rows(w, 11), "cg tank100 f32", S.SPH_F32)
     assert _walls_exact(w, X, w.rhs)
     Xb, repb = g.solve(w.rhs, S.SPH_F32, X0=w.x0, variant=S.SPH_ROBUST, **o)
     X64, _ = g.solve(w.rhs, S.SPH_F64, X0=w.x0, tol=1e-10, variant=S.SPH_CG, **o)

@@ -63,12 +63,36 @@ def test_increment_vanishes_on_constant_fields():
 
 
 def test_scalar_features_are_the_workload_parameters():
+    # constant viscosity: the relative-viscosity feature is 0, the stiffness
+    # feature is log10(dt nu / h^2)
     kw, pt, u, nu = _case(dt_nu=37.0)
     op = O.Operator(jacobi=False, **kw)
     S, _ = WS.samples(op, u, u, kw["mu"], kw["rho"], pt)
     fl = np.repeat(pt == W.FLUID, 3)
-    assert np.allclose(S[fl, 2], np.log10(nu), rtol=0, atol=1e-15)
+    assert np.allclose(S[fl, 2], 0.0, rtol=0, atol=1e-15)
     assert np.allclose(S[fl, 3], np.log10(37.0 / 1.3 ** 2), rtol=0, atol=1e-14)
+
+
+def test_viscosity_feature_is_scale_free():
+    # variable viscosity: feature 2 = log10 nu_k minus its mean over fluid
+    # rows (zero mean, the same when every viscosity is multiplied by 10),
+    # while the stiffness feature moves by exactly log10 10 = 1
+    kw, pt, u, nu = _case(dt_nu=20.0)
+    rng = np.random.default_rng(8)
+    mu = 10.0 ** rng.uniform(0.0, 2.0, pt.size)
+    kw = dict(kw, mu=mu)
+    op = O.Operator(jacobi=False, **kw)
+    S, _ = WS.samples(op, u, u, mu, kw["rho"], pt)
+    fl = pt == W.FLUID
+    f2 = S.reshape(-1, 3, 8)[fl, 0, 2]
+    assert abs(f2.mean()) < 1e-12
+    lognu = np.log10(mu / kw["rho"])[fl]
+    assert np.allclose(f2, lognu - lognu.mean(), rtol=0, atol=1e-13)
+    op10 = O.Operator(jacobi=False, **dict(kw, mu=10.0 * mu))
+    S10, _ = WS.samples(op10, u, u, 10.0 * mu, kw["rho"], pt)
+    assert np.allclose(S10[:, 2], S[:, 2], rtol=0, atol=1e-13)
+    f3 = S.reshape(-1, 3, 8)[fl, 0, 3]
+    assert np.allclose(S10.reshape(-1, 3, 8)[fl, 0, 3], f3 + 1.0, rtol=0, atol=1e-13)
 
 
 def test_jacobi_blend_is_second_order_in_dt():
