@@ -453,24 +453,42 @@ def kernel_comparison(ctx, n, steps, prec_name):
 
 
 def fp32_paper_study(ctx, n):
-    """The paper's all-FP32 solver (FP32 scalars, no residual restarts) on
-    the benchmark tank from the previous-step start and on a 64^3 plane
-    channel from rest: iterations, solve time and stalls of the robust and
-    textbook variants at 1e-6 and at the FP32 epsilon 2^-23, beside the
-    library's default (FP64 scalars, periodic true-residual restarts)."""
+    """Single-precision solvers (FP32 vectors and operator, FP32 scalars, no
+    residual restarts) against the library's default (FP64 scalars,
+    periodic true-residual restarts), robust and textbook variants, to 1e-6
+    and to the FP32 epsilon 2^-23, on: the benchmark tank from the
+    previous-step start; a 64^3 plane channel from rest; and the same channel
+    with a transverse component of noise of order 1e-8 (the situation in
+    which the paper observes single-precision stalls: a velocity component
+    that is analytically zero, its threshold near FLT_MIN).  Two
+    single-precision arithmetics: `f32s` rounds FP64-accumulated inner
+    products to FP32 (fp32_scalars), `paper32` is the paper's (FP32 matrix
+    from cell-relative positions, compensated FP32 gemv and inner products)."""
     import numpy as np
     import torch
 
     from paper_2206_14780_amd import sph as S
     from paper_2206_14780_amd import workloads as W
 
-    paper = dict(fp32_scalars=True, true_res_period=0, restart_drop=0.0)
-    runs = [("default_f64_scalars", S.SPH_ROBUST, {}),
-            ("paper_robust", S.SPH_ROBUST, paper), ("paper_standard", S.SPH_STANDARD, paper)]
+    f32s = dict(fp32_scalars=True, true_res_period=0, restart_drop=0.0)
+    p32 = dict(true_res_period=0, restart_drop=0.0)
+    runs = [("default_f64_scalars", S.SPH_ROBUST, {}, S.SPH_OP_CACHED),
+            ("f32s_robust", S.SPH_ROBUST, f32s, S.SPH_OP_CACHED),
+            ("f32s_standard", S.SPH_STANDARD, f32s, S.SPH_OP_CACHED),
+            ("paper32_robust", S.SPH_ROBUST, p32, S.SPH_OP_PAPER32),
+            ("paper32_standard", S.SPH_STANDARD, p32, S.SPH_OP_PAPER32)]
     out = {"workload": f"open-top tank {n}^3 (dummy walls) from the previous-step start; plane channel 64^3 "
-                       f"(dummy walls) from rest; FP32 vectors and operator, cached operator, max 3000 iterations",
-           "stall_note": "stalls counted on components with a nonzero right-hand side"}
-    for wname, w, use_x0 in (("tank", W.open_box(n=n), True), ("channel64", W.poiseuille(64, wall=W.WALL_DUMMY), False)):
+                       f"(dummy walls) from rest, and the same with a transverse rhs of N(0, 1e-8^2) noise; "
+                       f"FP32 vectors, cached operator, max 3000 iterations",
+           "stall_note": "stalls: iterations in which a component with a nonzero right-hand side broke down"}
+    chan = W.poiseuille(64, wall=W.WALL_DUMMY)
+    noisy = W.poiseuille(64, wall=W.WALL_DUMMY)
+    rng = np.random.default_rng(64)
+    noisy.rhs = noisy.rhs.copy()
+    fl = noisy.ptype == W.FLUID
+    noisy.rhs[fl, 1] = 1e-8 * rng.normal(size=int(fl.sum()))
+    for wname, w, use_x0 in (("tank", W.open_box(n=n), True), ("channel64", chan, False),
+                             ("channel64_transverse_noise", noisy, False)):
         parts = S.device_particles(w)
         dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
         nb = ctx.sph_build_neighbors(parts, dom)
@@ -478,10 +496,10 @@ def fp32_paper_study(ctx, n):
         start = w.x0 if use_x0 else np.zeros((w.n, 3))
         x0 = S.device_vec3(start, S.SPH_F32)
         live = [c for c in range(3) if np.any(w.rhs[:, c] != 0)]
-        params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=S.SPH_OP_CACHED)
         res = {}
         for tol_name, tol in (("tol_1e-6", 1e-6), ("tol_2^-23", 2.0 ** -23)):
-            for name, var, extra in runs:
+            for name, var, extra, mode in runs:
+                params = S.make_params(w.dt, w.wall, w.avg, jacobi=True, op_mode=mode)
                 x = [t.clone() for t in x0]
                 o = S.make_opts(tol=tol, x0_given=use_x0, max_iter=3000, variant=var, **extra)
                 rep = ctx.sph_visc_solve(nb, None, parts, params, S.SPH_F32, rhs, x, o)
@@ -490,13 +508,13 @@ def fp32_paper_study(ctx, n):
                     "status": rep["status"], "iterations": rep["iters"],
                     "solve_ms": round(rep["setup_ms"] + rep["iterate_ms"], 3),
                     "stalls": [rep["stall_count"][c] for c in live],
-                    "true_rel_res": [round(float(np.sqrt(rep["true_rr"][c] / rep["bb"][c])), 10) for c in live]}
+                    "states": [rep["state"][c] for c in live],
+                    "true_rel_res": [float(f"{np.sqrt(rep['true_rr'][c] / rep['bb'][c]):.4e}") for c in live]}
         nb.free()
         out[wname] = res
         print(f"[bench] fp32 study {wname}: {json.dumps(res)}", flush=True)
         del parts, rhs, x0
     return out
-
 
 def main():
     args = parse()

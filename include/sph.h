@@ -78,7 +78,7 @@ enum { SPH_KERNEL_WENDLAND = 0, SPH_KERNEL_GAUSSIAN = 1 };
 enum { SPH_WALL_DYNAMIC = 0, SPH_WALL_DUMMY = 1 }; /* boundary model (Section "Boundary conditions") */
 enum { SPH_AVG_ARITH = 0, SPH_AVG_HARMONIC = 1 };  /* pairwise viscosity mean (Section "Discretized equations") */
 enum { SPH_ROBUST = 0, SPH_STANDARD = 1, SPH_CG = 2 }; /* solver: robust / textbook BiCGSTAB, rotated CG */
-enum { SPH_OP_CACHED = 0, SPH_OP_ONTHEFLY = 1 };   /* operator evaluation (see sph_visc_params) */
+enum { SPH_OP_CACHED = 0, SPH_OP_ONTHEFLY = 1, SPH_OP_PAPER32 = 2 }; /* operator evaluation (see sph_visc_params) */
 enum { SPH_CONVERGED = 0, SPH_STATE_STALLED = 1, SPH_PROGRESSING = 2 }; /* per-component state */
 
 /* One particle configuration.  n >= 1; all arrays have n entries. */
@@ -107,13 +107,27 @@ typedef struct {
  *           FP64 and keeps the matrix in HBM (sliced ELLPACK, rounded to the
  *           vector precision) for all applications of that call;
  *           SPH_OP_ONTHEFLY re-evaluates the coefficients from positions in
- *           every application (the paper's matrix-free gemv). */
+ *           every application (the paper's matrix-free gemv);
+ *           SPH_OP_PAPER32 (SPH_F32 and the Wendland kernel only, else
+ *           SPH_E_ARG) is the paper's single-precision arithmetic (appendix
+ *           "Implementation notes", appendix on relative positions): every
+ *           pair weight evaluated in FP32 from FP32 positions relative to the
+ *           centres of the neighbour cells, the displacement of a pair grouped
+ *           as o' + (r'_b - r'_a) with o' = l (c_b - c_a) the FP32 offset of
+ *           the two cells (l the cell side); the diagonal 1 + dt sum w and the
+ *           dummy-wall normalisation sum W as compensated (Kahan) FP32 sums;
+ *           the matrix cached in FP32; the gemv y_r = A_rr x_r + sum A_ra x_a
+ *           with every product rounded to FP32 and the terms summed by Kahan's
+ *           compensation.  In sph_visc_solve it also makes every inner
+ *           product a compensated FP32 sum of FP32 products and every scalar
+ *           of the recurrences FP32 (as fp32_scalars); the true residual of
+ *           the library's final check stays FP64. */
 typedef struct {
     double dt;
     int32_t wall;    /* SPH_WALL_DYNAMIC / SPH_WALL_DUMMY */
     int32_t avg;     /* SPH_AVG_ARITH / SPH_AVG_HARMONIC */
     int32_t jacobi;  /* 0 / 1 */
-    int32_t op_mode; /* SPH_OP_CACHED / SPH_OP_ONTHEFLY */
+    int32_t op_mode; /* SPH_OP_CACHED / SPH_OP_ONTHEFLY / SPH_OP_PAPER32 */
 } sph_visc_params;
 
 /* Solver options.
@@ -161,13 +175,17 @@ typedef struct {
  *          whichever of the learned guess and the plain start (x on entry if
  *          x0_given, else zero) has the smaller FP64 true residual.  The
  *          tolerance and stopping test are unchanged.
- *   fp32_scalars: 1 = the paper's all-single-precision solver (appendix
- *          "Implementation notes"; SPH_F32 only, else SPH_E_ARG): every
- *          reduced inner product and every scalar of the recurrences (alpha,
- *          beta, omega, gamma, delta, tau^2) is rounded to FP32, the reduced
- *          sums standing for compensated (Kahan) FP32 sums; the vectors and
- *          the operator are FP32 as in SPH_F32.  Set true_res_period = 0 and
- *          restart_drop = 0 for the paper's unrestarted iteration.
+ *   fp32_scalars: 1 = FP32 scalars with FP64-accumulated inner products
+ *          (SPH_F32 only, else SPH_E_ARG): every reduced inner product, the
+ *          FP64 sum of the FP32 products, and every scalar of the recurrences
+ *          (alpha, beta, omega, gamma, delta, tau^2) is rounded to FP32; the
+ *          vectors and the operator are FP32 as in SPH_F32.  The inner
+ *          products are more accurate than the paper's single precision (an
+ *          FP64 sum keeps the low bits of products that cancel); the paper's
+ *          own arithmetic, compensated FP32 sums of FP32 products, is
+ *          params->op_mode = SPH_OP_PAPER32, which implies FP32 scalars.  Set
+ *          true_res_period = 0 and restart_drop = 0 for the paper's
+ *          unrestarted iteration.
  *   warm_u: device, n values of the caller's precision each: u.  A null
  *          component takes the initial guess (x0_given; the usual case of a
  *          previous-step start, which also saves one operator pass) or rhs. */

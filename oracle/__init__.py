@@ -75,6 +75,8 @@ def lib():
         L.orc_kahan_sum_f32.argtypes = [C.c_int64, fp]
         L.orc_kahan_dot_f32.restype = C.c_float
         L.orc_kahan_dot_f32.argtypes = [C.c_int64, fp, fp, fp]
+        L.orc_kahan_rows_f32.argtypes = [C.c_int64, i64p, fp, fp]
+        L.orc_kahan_gemv_f32.argtypes = [C.c_int64, i64p, i32p, fp, fp, fp, fp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L

@@ -62,25 +62,200 @@ def _dot_w(D, a, b, dots="f64"):
     return (D[:, None] * a.astype(np.float64) * b.astype(np.float64)).sum(axis=0).astype(F32)
 
 
+# ---------------------------------------------------------------------------
+# The paper's single-precision matrix (appendix on relative positions,
+# appendix "Implementation notes"): pair weights in FP32 from FP32 positions
+# relative to cell centres, the cell grid being that of the neighbour
+# search (cells of side >= the support, see `cell_grid`); diagonal and
+# dummy-wall normalisation as Kahan FP32 sums; the gemv with FP32 products
+# summed by Kahan's compensation.
+# ---------------------------------------------------------------------------
+
+def cell_grid(lo, hi, periodic, h, support=2.0):
+    """(nc, cs, period) per axis: nc = max(1, floor(L / (s (1 + 1e-9)))) cells
+    of side L / nc (twice L for a single cell on a non-periodic axis), s the
+    support radius; the period is L on periodic axes, else 0."""
+    s = float(support) * float(h)
+    target = s * (1.0 + 1e-9)
+    nc = np.zeros(3, dtype=np.int64)
+    cs = np.zeros(3)
+    period = np.zeros(3)
+    for a in range(3):
+        L = float(hi[a]) - float(lo[a])
+        n = max(int(np.floor(L / target)), 1)
+        nc[a] = n
+        cs[a] = L / n if L > 0.0 else 1.0
+        if not periodic[a] and n == 1:
+            cs[a] = 2.0 * L if L > 0.0 else 1.0
+        period[a] = L if periodic[a] else 0.0
+    return nc, cs, period
+
+
+def _disp(d, period):
+    return d - period * np.rint(d / period) if period > 0.0 else d
+
+
+def cell_relative(pos, lo, nc, cs, period):
+    """Integer cell coordinates (n, 3) (floor of (x - lo)/cs, wrapped on periodic
+    axes, clamped on the others) and the FP32 offsets (n, 3) from the cell
+    centres lo + (c + 1/2) cs (minimum image on periodic axes)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    c = np.zeros(pos.shape, dtype=np.int64)
+    r = np.zeros(pos.shape, dtype=F32)
+    for a in range(3):
+        u = np.floor((pos[:, a] - lo[a]) / cs[a]).astype(np.int64)
+        u = np.mod(u, nc[a]) if period[a] > 0.0 else np.clip(u, 0, nc[a] - 1)
+        c[:, a] = u
+        centre = lo[a] + (u.astype(np.float64) + 0.5) * cs[a]
+        r[:, a] = _disp(pos[:, a] - centre, period[a]).astype(F32)
+    return c, r
+
+
+class Paper32Operator:
+    """The paper's single-precision matrix of one system (Wendland kernel),
+    Jacobi scaled or not, on the oracle's neighbour lists (rows in original
+    order, columns ascending).
+
+    Pair (row b, neighbour a), per axis: o = l (c_b - c_a) as the FP32 product
+    of the cell side and the integer cell difference (on periodic axes plus
+    the multiple of the cell count that the FP64 minimum image takes), then
+    d = o + (r'_b - r'_a) in FP32; r2 = (d0^2 + d1^2) + d2^2; q = sqrt(r2) / h;
+    F = (105/(128 pi) (q - 2)^3) / h^5 and W = 21/(16 pi) (1 - q/2)^4 (2q + 1)
+    / h^3 for q < 2; w = -((2 mubar (m_a / rho_a)) F) / rho_b, 2 mubar = mu_a
+    + mu_b or 4 mu_a mu_b / (mu_a + mu_b) -- every operation in FP32 on the
+    FP32-rounded particle data.  Fluid row: D = 1 + dt (Kahan sum of w), off
+    entries -(dt w), divided by D when scaled; plain diagonal 1 (scaled) or D.
+    Dummy-wall row: W / (Kahan sum of W) over fluid neighbours (identity when
+    that sum is 0); identity rows otherwise."""
+
+    def __init__(self, op: Operator, lo, hi, periodic):
+        if op.kernel != 0:
+            raise ValueError("the single-precision matrix is defined for the Wendland kernel")
+        from . import lib, _dp
+        import ctypes as C
+        n = op.n
+        pos = np.stack([op._x, op._y, op._z], axis=1)
+        nc, cs, period = cell_grid(lo, hi, periodic, op.h, 2.0)
+        cell, rel = cell_relative(pos, np.asarray(lo, np.float64), nc, cs, period)
+        rp, cols = op.row_ptr, op.cols
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        a = cols.astype(np.int64)
+        d = np.zeros((rows.size, 3), dtype=F32)
+        for k in range(3):
+            dc = cell[rows, k] - cell[a, k]
+            rb, ra = rel[rows, k], rel[a, k]
+            if period[k] > 0.0:
+                d64 = _disp(pos[rows, k] - pos[a, k], period[k])
+                rest = d64 - dc.astype(np.float64) * cs[k] - (rb.astype(np.float64) - ra.astype(np.float64))
+                dc = dc + np.rint(rest / period[k]).astype(np.int64) * nc[k]
+            o = F32(cs[k]) * dc.astype(F32)
+            d[:, k] = o + (rb - ra)
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        hf = F32(op.h)
+        inv_h = 1.0 / op.h
+        inv_h3 = inv_h * inv_h * inv_h
+        inv_h5 = inv_h3 * inv_h * inv_h
+        with np.errstate(all="ignore"):
+            q = np.sqrt(r2) / hf
+            inside = q < F32(2.0)
+            t = q - F32(2.0)
+            F = np.where(inside, (F32(105.0 / (128.0 * np.pi)) * ((t * t) * t)) * F32(inv_h5), F32(0.0))
+            u = F32(1.0) - F32(0.5) * q
+            W = np.where(inside, ((F32(21.0 / (16.0 * np.pi)) * (((u * u) * u) * u))
+                                  * (F32(2.0) * q + F32(1.0))) * F32(inv_h3), F32(0.0))
+            mu = op._mu.astype(F32)
+            m = op._mass.astype(F32)
+            rho = op._rho.astype(F32)
+            mua, mub = mu[a], mu[rows]
+            if op.avg == 1:
+                ssum = mua + mub
+                tm = np.where(ssum > F32(0.0), (F32(4.0) * (mua * mub)) / ssum, F32(0.0))
+            else:
+                tm = mua + mub
+            w = -((tm * (m[a] / rho[a])) * F) / rho[rows]
+        w = w.astype(F32)
+        W = W.astype(F32)
+        fluid = op._type == FLUID_TYPE
+        fp = C.POINTER(C.c_float)
+        i64p = C.POINTER(C.c_int64)
+        L = lib()
+
+        def rowsum(v):
+            v = np.ascontiguousarray(v, dtype=F32)
+            out = np.zeros(n, dtype=F32)
+            L.orc_kahan_rows_f32(n, rp.ctypes.data_as(i64p), v.ctypes.data_as(fp), out.ctypes.data_as(fp))
+            return out
+
+        dt = F32(op.dt)
+        Sw = rowsum(np.where(fluid[rows], w, F32(0.0)))
+        D = np.where(fluid, F32(1.0) + dt * Sw, F32(1.0)).astype(F32)
+        Wf = np.where(fluid[a] & ~fluid[rows], W, F32(0.0)).astype(F32)
+        SW = rowsum(Wf)
+        aba = -(dt * w)
+        off = np.where(fluid[rows], aba / D[rows] if op.jacobi else aba, F32(0.0)).astype(F32)
+        dummy = (~fluid[rows]) & (op.wall == 1) & (SW[rows] > F32(0.0))
+        with np.errstate(all="ignore"):
+            off = np.where(dummy, Wf / SW[rows], off).astype(F32)
+        self.n, self.row_ptr, self.cols = n, rp, cols
+        self.off = np.ascontiguousarray(off, dtype=F32)
+        self.D = D                                          # FP32 diagonal 1 + dt sum w (1 on walls)
+        self.diag = np.where(fluid & (not op.jacobi), D, F32(1.0)).astype(F32)  # the plain A_bb
+        self.jacobi = op.jacobi
+        self.cell, self.rel = cell, rel
+
+    def apply(self, X):
+        """Y (n, 3) FP32 = the Kahan FP32 gemv of X (rounded to FP32)."""
+        from . import lib
+        import ctypes as C
+        fp = C.POINTER(C.c_float)
+        X = np.asarray(X, dtype=F32)
+        Y = np.zeros(X.shape, dtype=F32)
+        for c in range(3):
+            x = np.ascontiguousarray(X[:, c])
+            y = np.zeros(self.n, dtype=F32)
+            lib().orc_kahan_gemv_f32(self.n, self.row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     self.cols.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     self.diag.ctypes.data_as(fp), self.off.ctypes.data_as(fp),
+                                     x.ctypes.data_as(fp), y.ctypes.data_as(fp))
+            Y[:, c] = y
+        return Y
+
+    def rhs(self, B):
+        """The scaled right-hand side FP32(B) / D (rounded once), or FP32(B)."""
+        b = np.asarray(B, dtype=F32).astype(np.float64)
+        if self.jacobi:
+            b = b / self.D.astype(np.float64)[:, None]
+        return b.astype(F32)
+
+
 def _rhs(op: Operator, B):
     b = np.asarray(B, dtype=np.float64)
     return b / op.diag()[:, None] if op.jacobi else b
 
 
-def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_stall=None, dots="f64"):
+def solve(op: Operator, B, tol=2.0 ** -23, max_iter=2000, variant=ROBUST, force_stall=None, dots="f64",
+          paper32: "Paper32Operator" = None):
     """A V = B (three columns) in single precision.  Returns (X (n, 3) FP32,
     report dict with iters, state, stall_count, rr, tau2, and history
-    (iters + 1, 3) of r.r).  dots: "f64" or "kahan" (see the module)."""
+    (iters + 1, 3) of r.r).  dots: "f64" or "kahan" (see the module);
+    paper32: the paper's single-precision matrix and gemv instead of the
+    FP64 operator rounded to FP32."""
     if dots not in _DOTS:
         raise ValueError(dots)
 
     def dot(a, b):
         return _dot(a, b, dots)
 
-    def A(v):
-        return op.apply(v.astype(np.float64)).astype(F32)
+    if paper32 is not None:
+        def A(v):
+            return paper32.apply(v)
 
-    b = _rhs(op, B).astype(F32)
+        b = paper32.rhs(B)
+    else:
+        def A(v):
+            return op.apply(v.astype(np.float64)).astype(F32)
+
+        b = _rhs(op, B).astype(F32)
     x = np.zeros_like(b)
     r = b.copy()
     rh = r.copy()

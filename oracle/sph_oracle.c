@@ -682,6 +682,50 @@ float orc_kahan_dot_f32(int64_t n, const float *w, const float *a, const float *
     return s;
 }
 
+/* out[b] = Kahan's FP32 sum of v[row_ptr[b] .. row_ptr[b+1]) in order, its
+ * zero terms skipped. */
+void orc_kahan_rows_f32(int64_t n, const int64_t *row_ptr, const float *v, float *out) {
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t b = 0; b < n; ++b) {
+        float s = 0.0f, c = 0.0f;
+        for (int64_t k = row_ptr[b]; k < row_ptr[b + 1]; ++k) {
+            if (v[k] == 0.0f) continue;
+            float y = v[k] - c;
+            float t = s + y;
+            c = (t - s) - y;
+            s = t;
+        }
+        out[b] = s;
+    }
+}
+
+/* The single-precision gemv: y_b = A_bb x_b + sum_k A_b,cols[k] x_cols[k],
+ * every product rounded to FP32, the terms (diagonal first, then the stored
+ * entries in order, zero entries skipped) summed with Kahan's compensation. */
+void orc_kahan_gemv_f32(int64_t n, const int64_t *row_ptr, const int32_t *cols, const float *diag,
+                        const float *off, const float *x, float *y) {
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t b = 0; b < n; ++b) {
+        float s = 0.0f, c = 0.0f;
+        float terms0 = diag[b] * x[b];
+        {
+            float yy = terms0 - c;
+            float t = s + yy;
+            c = (t - s) - yy;
+            s = t;
+        }
+        for (int64_t k = row_ptr[b]; k < row_ptr[b + 1]; ++k) {
+            if (off[k] == 0.0f) continue;
+            float p = off[k] * x[cols[k]];
+            float yy = p - c;
+            float t = s + yy;
+            c = (t - s) - yy;
+            s = t;
+        }
+        y[b] = s;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* BiCGSTAB for d = 3 systems sharing one matrix.                            */
 /* ------------------------------------------------------------------------ */

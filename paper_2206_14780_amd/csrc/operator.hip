@@ -411,10 +411,20 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
     double* wl = wlist + (r / kWave) * ((int64_t)cap * kWave) + r % kWave;  // entry k at wl[k * kWave]
     const Pos4 pb = nv.pos[row];
     const double mu_b = pv.mu[row], ir_b = pv.inv_rho[row];
+    const bool f32 = op.f32cell != 0;
     const auto weight = [&](int32_t a, double r2) {
         if (kind != kRowFluid) return pair_W(g, r2);
         const double2 ma = pv.mu_mr[a];
         return pair_w_v(g, op.avg, ma.x, ma.y, mu_b, ir_b, r2);
+    };
+    // the paper's single precision: FP32 weight from cell-relative positions
+    const int32_t cb = nv.scell[row];
+    const float mub32 = (float)mu_b, rhob32 = (float)pv.rho[row];
+    const auto weight32 = [&](int32_t a) -> double {
+        const float r2 = dist2_f32(g, pb, cb, nv.pos[a], nv.scell[a]);
+        if (kind != kRowFluid) return (double)wendland_W_f32(g, r2);
+        return (double)pair_w_f32(g, op.avg, (float)pv.mu[a], (float)pv.mass[a], (float)pv.rho[a], mub32, rhob32,
+                                  r2);
     };
     // r^2 exactly as the scan computes it
     const auto dist2 = [&](int32_t a) {
@@ -431,19 +441,33 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
         });
     };
     double sum = 0.0;
+    float sum32 = 0.f, cmp32 = 0.f;  // compensated FP32 sum (f32)
+    const auto add = [&](double w) {
+        if (f32) kahan_add(sum32, cmp32, (float)w);
+        else sum += w;
+    };
     if (listed) {
         for (int32_t k = 0; k < c; ++k) {
             const int32_t a = lst[list_off(k)];
-            const double w = weight(a, dist2(a));
+            const double w = f32 ? weight32(a) : weight(a, dist2(a));
             wl[k * kWave] = w;
-            sum += w;
+            add(w);
         }
     } else {
-        scan([&](int32_t a, double r2) { sum += weight(a, r2); });
+        scan([&](int32_t a, double r2) { add(f32 ? weight32(a) : weight(a, r2)); });
     }
-    const double D = kind == kRowFluid ? 1.0 + op.dt * sum : 1.0;
+    if (f32) sum = (double)sum32;
+    const float D32 = kind == kRowFluid ? 1.0f + (float)op.dt * sum32 : 1.0f;
+    const double D = f32 ? (double)D32 : (kind == kRowFluid ? 1.0 + op.dt * sum : 1.0);
     if (kind == kRowDummy && !(sum > 0.0)) c = 0;  // identity row
     const auto coefficient = [&](double w) {
+        if (f32) {
+            if (kind == kRowFluid) {
+                const float aba = -((float)op.dt * (float)w);
+                return (double)(op.jacobi ? aba / D32 : aba);
+            }
+            return (double)((float)w / sum32);
+        }
         if (kind == kRowFluid) {
             const double aba = -op.dt * w;
             return op.jacobi ? aba / D : aba;
@@ -453,27 +477,41 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
     const int32_t width = (int32_t)((sl_ptr[s + 1] - sl_ptr[s]) / kWave);
     RowWriter<T> wr{coef, dcol, lo, lane_base<T>(sl_ptr[s], r % kWave)};
     int32_t first = row;
+    double csum = 0.0;  // f32: FP64 sum of the stored coefficients
     if (listed) {
         for (int32_t k = 0; k < c; ++k) {
             const int32_t a = lst[list_off(k)];
             if (k == 0) first = a;
-            wr.put(a, coefficient(wl[k * kWave]));
+            const double cv = coefficient(wl[k * kWave]);
+            csum += cv;
+            wr.put(a, cv);
         }
     } else if (c > 0) {
         scan([&](int32_t a, double r2) {
             if (wr.j == 0) first = a;
-            wr.put(a, coefficient(weight(a, r2)));
+            const double cv = coefficient(f32 ? weight32(a) : weight(a, r2));
+            csum += cv;
+            wr.put(a, cv);
         });
     }
     wr.pad(width);
     if (valid) {
         c0[row] = first;
-        // row sums: 1/A_rr (Jacobi) or 1 on fluid rows (eqs. diag, offdiag),
-        // 2 on dummy rows with fluid neighbours (eq. implicit-system-dummy-full),
-        // 1 on identity rows
-        const double rs = kind == kRowFluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
-        dg[row] = (T)rs;
-        rs64[row] = rs;
+        if (f32) {
+            // the plain diagonal A_rr (1 when scaled, on identity and on
+            // dummy rows); the FP64 row sum of the stored FP32 matrix for
+            // the difference form of the true residual
+            const double dd = kind == kRowFluid && !op.jacobi ? D : 1.0;
+            dg[row] = (T)dd;
+            rs64[row] = dd + csum;
+        } else {
+            // row sums: 1/A_rr (Jacobi) or 1 on fluid rows (eqs. diag, offdiag),
+            // 2 on dummy rows with fluid neighbours (eq. implicit-system-dummy-full),
+            // 1 on identity rows
+            const double rs = kind == kRowFluid ? (op.jacobi ? 1.0 / D : 1.0) : (c > 0 ? 2.0 : 1.0);
+            dg[row] = (T)rs;
+            rs64[row] = rs;
+        }
         diag64[row] = D;
     }
 }
@@ -497,7 +535,9 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
     // Test hook: the environment variable SPH_BUILD_LEGACY=1 selects the
     // build that evaluates the coefficients inside the neighbour scan, the
     // reference the list-based build is tested against bit for bit.
-    const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0;
+    if (op.f32cell && nb->g.kernel != SPH_KERNEL_WENDLAND)
+        return ctx->fail(SPH_E_ARG, "SPH_OP_PAPER32 is defined for the Wendland kernel");
+    const bool legacy = env_int("SPH_BUILD_LEGACY", 0) > 0 && !op.f32cell;
     // list entries per row: room for every neighbour of the kernel's support
     // (int32 index + FP64 weight each) while that fits the budget
     const int32_t cap = nb->g.kernel == SPH_KERNEL_GAUSSIAN &&
@@ -618,7 +658,14 @@ template <typename T>
 sph_status apply_plain(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const OpParams& op, int mode,
                        const Sell<T>* sell, const T* x, T* y) {
     const Launch L = make_launch(nb->n);
-    if (mode == SPH_OP_CACHED) {
+    if (mode == SPH_OP_PAPER32) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_apply_sell<T, kDotNone, T, true>), dim3(L.grid_apply), dim3(L.block_apply), 0,
+                               ctx->stream, (const int32_t*)nullptr, nb->n, *sell, x, y, (const T*)nullptr,
+                               (const double*)nullptr, (double*)nullptr);
+        else
+            return ctx->fail(SPH_E_ARG, "apply: SPH_OP_PAPER32 is single precision");
+    } else if (mode == SPH_OP_CACHED) {
         hipLaunchKernelGGL((k_apply_sell<T, kDotNone>), dim3(L.grid_apply), dim3(L.block_apply), 0, ctx->stream,
                            (const int32_t*)nullptr, nb->n, *sell, x, y, (const T*)nullptr, (const double*)nullptr,
                            (double*)nullptr);
@@ -652,8 +699,11 @@ sph_status check_params(sph_ctx* ctx, const sph_visc_params* v, int32_t prec) {
     if (!(v->dt >= 0.0) || !std::isfinite(v->dt)) return ctx->fail(SPH_E_ARG, "params: dt must be finite and >= 0");
     if (v->wall != SPH_WALL_DYNAMIC && v->wall != SPH_WALL_DUMMY) return ctx->fail(SPH_E_ARG, "params: wall");
     if (v->avg != SPH_AVG_ARITH && v->avg != SPH_AVG_HARMONIC) return ctx->fail(SPH_E_ARG, "params: avg");
-    if (v->op_mode != SPH_OP_CACHED && v->op_mode != SPH_OP_ONTHEFLY) return ctx->fail(SPH_E_ARG, "params: op_mode");
+    if (v->op_mode != SPH_OP_CACHED && v->op_mode != SPH_OP_ONTHEFLY && v->op_mode != SPH_OP_PAPER32)
+        return ctx->fail(SPH_E_ARG, "params: op_mode");
     if (prec != SPH_F32 && prec != SPH_F64) return ctx->fail(SPH_E_ARG, "prec");
+    if (v->op_mode == SPH_OP_PAPER32 && prec != SPH_F32)
+        return ctx->fail(SPH_E_ARG, "params: SPH_OP_PAPER32 is single precision (SPH_F32)");
     return SPH_OK;
 }
 
@@ -668,7 +718,8 @@ static sph_status apply_entry(sph_ctx* ctx, const sph_nbr* nb, const sph_particl
     SPH_TRY(ctx->ensure_t(kApplyOut, (size_t)nb->n * 3, &yout));
     SPH_TRY(gather_vec3<T>(ctx, nb, x, xin));
     Sell<T> sell{};
-    if (v->op_mode == SPH_OP_CACHED) SPH_TRY(build_sell<T>(ctx, nb, pv, op, &sell, nullptr));
+    if (v->op_mode == SPH_OP_PAPER32) op.f32cell = 1;
+    if (v->op_mode != SPH_OP_ONTHEFLY) SPH_TRY(build_sell<T>(ctx, nb, pv, op, &sell, nullptr));
     SPH_TRY(apply_plain<T>(ctx, nb, pv, op, v->op_mode, &sell, xin, yout));
     SPH_TRY(scatter_vec3<T>(ctx, nb, yout, y));
     return SPH_OK;

@@ -26,28 +26,30 @@ struct DotK {
                              : MODE == kDotResid ? 3 : MODE == kDotCG ? 3 : 1;
 };
 
-template <typename T, int MODE>
-__device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], V3<T> xs, V3<T> yv, V3<T> wv,
-                                       double dw = 1.0) {
+// KH: the paper's single precision (products rounded to FP32, compensated
+// FP32 sums; see kahan_add), else FP64 products and sums.
+template <typename T, int MODE, bool KH = false>
+__device__ inline void accumulate_dots(double (&acc)[DotK<MODE>::K], float (&cmp)[DotK<MODE>::K], V3<T> xs,
+                                       V3<T> yv, V3<T> wv, double dw = 1.0) {
     if constexpr (MODE == kDotCG) {
-        acc[0] += dw * (double)xs.x * (double)yv.x;
-        acc[1] += dw * (double)xs.y * (double)yv.y;
-        acc[2] += dw * (double)xs.z * (double)yv.z;
+        dot_add_w<KH>(acc[0], cmp[0], dw, (double)xs.x, (double)yv.x);
+        dot_add_w<KH>(acc[1], cmp[1], dw, (double)xs.y, (double)yv.y);
+        dot_add_w<KH>(acc[2], cmp[2], dw, (double)xs.z, (double)yv.z);
     } else if constexpr (MODE == kDotA1) {
-        acc[0] += (double)wv.x * (double)yv.x;
-        acc[1] += (double)wv.y * (double)yv.y;
-        acc[2] += (double)wv.z * (double)yv.z;
+        dot_add<KH>(acc[0], cmp[0], (double)wv.x, (double)yv.x);
+        dot_add<KH>(acc[1], cmp[1], (double)wv.y, (double)yv.y);
+        dot_add<KH>(acc[2], cmp[2], (double)wv.z, (double)yv.z);
     } else if constexpr (MODE == kDotA2 || MODE == kDotA2Std) {
-        acc[0] += (double)xs.x * (double)yv.x;
-        acc[1] += (double)xs.y * (double)yv.y;
-        acc[2] += (double)xs.z * (double)yv.z;
-        acc[3] += (double)yv.x * (double)yv.x;
-        acc[4] += (double)yv.y * (double)yv.y;
-        acc[5] += (double)yv.z * (double)yv.z;
+        dot_add<KH>(acc[0], cmp[0], (double)xs.x, (double)yv.x);
+        dot_add<KH>(acc[1], cmp[1], (double)xs.y, (double)yv.y);
+        dot_add<KH>(acc[2], cmp[2], (double)xs.z, (double)yv.z);
+        dot_add<KH>(acc[3], cmp[3], (double)yv.x, (double)yv.x);
+        dot_add<KH>(acc[4], cmp[4], (double)yv.y, (double)yv.y);
+        dot_add<KH>(acc[5], cmp[5], (double)yv.z, (double)yv.z);
         if constexpr (MODE == kDotA2Std) {
-            acc[6] += (double)xs.x * (double)xs.x;
-            acc[7] += (double)xs.y * (double)xs.y;
-            acc[8] += (double)xs.z * (double)xs.z;
+            dot_add<KH>(acc[6], cmp[6], (double)xs.x, (double)xs.x);
+            dot_add<KH>(acc[7], cmp[7], (double)xs.y, (double)xs.y);
+            dot_add<KH>(acc[8], cmp[8], (double)xs.z, (double)xs.z);
         }
     }
 }
@@ -178,13 +180,59 @@ __device__ inline void sell_row(const Sell<T>& A, int64_t base, int32_t width, i
     }
 }
 
+// The paper's single-precision gemv of one row: y_r = A_rr x_r + sum_k
+// coef[r,k] x[col[r,k]] with every product rounded to FP32 and the terms
+// added in slot order by Kahan's compensated summation (zero-weight escape
+// and padding slots add nothing).  d: the plain diagonal A_rr.
+__device__ inline void sell_row_kahan(const Sell<float>& A, int64_t base, int32_t width, int32_t row,
+                                      const float* __restrict__ x, const V3<float>& xs, float d, V3<float>& y) {
+    constexpr int kGroup = group_of<float, false>();
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    kahan_add(s0, c0, d * xs.x);
+    kahan_add(s1, c1, d * xs.y);
+    kahan_add(s2, c2, d * xs.z);
+    int32_t col = A.c0[row];
+    float rw[kGroup];
+    uint16_t rd[kGroup];
+    double rl[kGroup];
+    sell_group<float, false>(A, base, width, 0, rw, rd, rl);
+    for (int32_t k0 = 0; k0 < width; k0 += kGroup) {
+        int32_t cc[kGroup];
+        float cw[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const bool esc = rd[u] == kEscape;
+            col += esc ? jump_bits(rw[u]) : (int32_t)rd[u];
+            cw[u] = esc ? 0.f : rw[u];
+            cc[u] = cw[u] == 0.f ? row : col;
+        }
+        V3<float> xv[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) xv[u] = ld3(x, cc[u]);
+        sell_group<float, false>(A, base, width, k0 + kGroup, rw, rd, rl);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if (cw[u] != 0.f) {
+                kahan_add(s0, c0, cw[u] * xv[u].x);
+                kahan_add(s1, c1, cw[u] * xv[u].y);
+                kahan_add(s2, c2, cw[u] * xv[u].z);
+            }
+        }
+    }
+    y = V3<float>{s0, s1, s2};
+}
+
 // Cached operator: y_r = rs_r x_r + sum_k coef[r,k] (x[col[r,k]] - x_r).
 // One wavefront per 64-row slice; each block takes a contiguous range of
 // slices (XCD-aware order) and its waves interleave over it.  With kDotResid
 // the kernel writes y = b64 - A x (FP64-accurate, rounded to T) instead, and
 // x may be held in another precision XT; with kDotCG, b64 holds the weights
 // D of the inner product.
-template <typename T, int MODE, typename XT = T>
+//
+// KH (T = float only): the paper's single precision: the row in plain form
+// with compensated FP32 sums (sell_row_kahan, A.dg the plain diagonal) and
+// the inner products of FP32 products with compensated FP32 sums.
+template <typename T, int MODE, typename XT = T, bool KH = false>
 __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __restrict__ halt, int64_t n, Sell<T> A,
                                                           const XT* __restrict__ x, T* __restrict__ y,
                                                           const T* __restrict__ w, const double* __restrict__ b64,
@@ -192,10 +240,15 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __
     if (halt && *halt) return;
     constexpr int K = DotK<MODE>::K;
     constexpr bool RES = MODE == kDotResid;
-    __shared__ double lds[K * kMaxWaves];
+    static_assert(!KH || (sizeof(T) == 4 && !RES), "single-precision arithmetic: FP32 operator, not the residual");
+    __shared__ double lds[(KH ? 2 : 1) * K * kMaxWaves];
     double acc[K];
+    float cmp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        acc[k] = 0.0;
+        cmp[k] = 0.f;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
@@ -222,24 +275,28 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_sell(const int32_t* __
             acc[2] += r2 * r2;
             st3(y, row, V3<T>{(T)r0, (T)r1, (T)r2});
         } else {
-            T a0 = T(0), a1 = T(0), a2 = T(0);
-            sell_row<T, false>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
-            const T d = A.dg[row];
             V3<T> yv;
-            yv.x = fma_t(d, xs.x, a0);
-            yv.y = fma_t(d, xs.y, a1);
-            yv.z = fma_t(d, xs.z, a2);
+            if constexpr (KH) {
+                sell_row_kahan(A, base, width, (int32_t)row, x, xs, A.dg[row], yv);
+            } else {
+                T a0 = T(0), a1 = T(0), a2 = T(0);
+                sell_row<T, false>(A, base, width, (int32_t)row, x, xs, a0, a1, a2);
+                const T d = A.dg[row];
+                yv.x = fma_t(d, xs.x, a0);
+                yv.y = fma_t(d, xs.y, a1);
+                yv.z = fma_t(d, xs.z, a2);
+            }
             st3(y, row, yv);
             if constexpr (MODE != kDotNone) {
                 V3<T> wv{};
                 if constexpr (MODE == kDotA1) wv = ld3(w, row);
                 double dw = 1.0;
                 if constexpr (MODE == kDotCG) dw = b64 ? b64[row] : 1.0;
-                accumulate_dots<T, MODE>(acc, xs, yv, wv, dw);
+                accumulate_dots<T, MODE, KH>(acc, cmp, xs, yv, wv, dw);
             }
         }
     }
-    if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);
+    if constexpr (MODE != kDotNone) write_partials_kh<K, KH>(acc, cmp, lds, part);
 }
 
 // One row of the operator evaluated from positions in FP64 (the paper's
@@ -329,7 +386,8 @@ __global__ __launch_bounds__(kApplyMaxBlock) void k_apply_otf(const int32_t* __r
             if constexpr (MODE == kDotA1) wv = ld3(w, r);
             double dw = 1.0;
             if constexpr (MODE == kDotCG) dw = b64 ? b64[r] : 1.0;
-            accumulate_dots<T, MODE>(acc, ld3(x, r), out, wv, dw);
+            float cmp[K];
+            accumulate_dots<T, MODE>(acc, cmp, ld3(x, r), out, wv, dw);
         }
     }
     if constexpr (MODE != kDotNone) write_partials<K>(acc, lds, part);

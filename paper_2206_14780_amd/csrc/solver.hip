@@ -46,14 +46,18 @@ __device__ inline void rsc_all(const SolveConst& sc, double (&v)[K]) {
 
 // Initial residual: r = b - A x0 given in `r0` (null: x0 = 0, r = b),
 // r0hat = r; partials of r0hat . r, r . r and b . b.
-template <typename T>
+template <typename T, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_init(int64_t n, const T* __restrict__ b, const T* __restrict__ r0,
                                                     T* __restrict__ r, T* __restrict__ rh0,
                                                     double* __restrict__ part) {
-    __shared__ double lds[kKp * kMaxWaves];
+    __shared__ double lds[2 * kKp * kMaxWaves];
     double acc[kKp];
+    float cmp[kKp];
 #pragma unroll
-    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kKp; ++k) {
+        acc[k] = 0.0;
+        cmp[k] = 0.f;
+    }
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
     const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
@@ -66,12 +70,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_init(int64_t n, const T* __restri
         const double bb[3] = {(double)bv.x, (double)bv.y, (double)bv.z};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            acc[c] += q[c] * q[c];
-            acc[3 + c] += q[c] * q[c];
-            acc[6 + c] += bb[c] * bb[c];
+            dot_add<KH>(acc[c], cmp[c], q[c], q[c]);
+            dot_add<KH>(acc[3 + c], cmp[3 + c], q[c], q[c]);
+            dot_add<KH>(acc[6 + c], cmp[6 + c], bb[c], bb[c]);
         }
     }
-    write_partials<kKp>(acc, lds, part);
+    write_partials_kh<kKp, KH>(acc, cmp, lds, part);
 }
 
 // Scalars of the p update of iteration `it`, i.e. the outcome of iteration
@@ -191,7 +195,7 @@ __device__ inline void p_scalars(const Ctl* __restrict__ ctl, int32_t it, const 
 
 // CG: dw (null: 1) weighs the partials of rho = <r, r>_D written to
 // part_rho, taken after any restart copy (the r that p is built from).
-template <typename T>
+template <typename T, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                     const double* __restrict__ part, int32_t nblk,
                                                     const double* __restrict__ part_tr, int64_t n, T* __restrict__ r,
@@ -200,9 +204,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
                                                     double* __restrict__ hist, int32_t* __restrict__ stallhist,
                                                     const double* __restrict__ dw, double* __restrict__ part_rho) {
     if (ctl->halt) return;
-    __shared__ double lds[kKp * kMaxWaves];
+    __shared__ double lds[2 * kKp * kMaxWaves];
     double red[kKp];
-    reduce_partials<kKp>(part, nblk, red, lds);
+    reduce_partials_kh<kKp, KH>(part, nblk, red, lds);
     rsc_all(sc, red);
     const int32_t j = it - 1;
     // periodic FP64 true residual of iteration j, unless a host-issued check
@@ -259,6 +263,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
     double om[3];
     for (int c = 0; c < 3; ++c) om[c] = !textbook ? 0.0 : (it > 1 ? ctl->omega[j & 1][c] : 1.0);
     double acc[3] = {0.0, 0.0, 0.0};
+    float cmp[3] = {0.f, 0.f, 0.f};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
     const int64_t i0 = bid * rpb, i1 = min(i0 + rpb, n);
@@ -290,24 +295,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupd(Ctl* __restrict__ ctl, int32
         st3(p, i, V3<T>{o[0], o[1], o[2]});
         if (part_rho) {
             const double d = dw ? dw[i] : 1.0;
-            acc[0] += d * (double)rv.x * (double)rv.x;
-            acc[1] += d * (double)rv.y * (double)rv.y;
-            acc[2] += d * (double)rv.z * (double)rv.z;
+            dot_add_w<KH>(acc[0], cmp[0], d, (double)rv.x, (double)rv.x);
+            dot_add_w<KH>(acc[1], cmp[1], d, (double)rv.y, (double)rv.y);
+            dot_add_w<KH>(acc[2], cmp[2], d, (double)rv.z, (double)rv.z);
         }
     }
-    if (part_rho) write_partials<3>(acc, lds, part_rho);
+    if (part_rho) write_partials_kh<3, KH>(acc, cmp, lds, part_rho);
 }
 
 // alpha_i = gamma_i/delta_i, then s = r - alpha A p.
-template <typename T>
+template <typename T, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                     const double* __restrict__ part, int32_t nblk, int64_t n,
                                                     const T* __restrict__ r, const T* __restrict__ ap,
                                                     T* __restrict__ s) {
     if (ctl->halt) return;
-    __shared__ double lds[3 * kMaxWaves];
+    __shared__ double lds[2 * 3 * kMaxWaves];
     double red[3];
-    reduce_partials<3>(part, nblk, red, lds);
+    reduce_partials_kh<3, KH>(part, nblk, red, lds);
     rsc_all(sc, red);
     const int cur = it & 1;
     double al[3];
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_supd(Ctl* __restrict__ ctl, int32
 // omega_i = (s . A s)/(A s . A s); x = x + alpha p + omega s; r = s - omega A s;
 // partials of r0hat . r and r . r.  x is held in X (T, or FP64 under an FP32
 // operator: then the update is evaluated in FP64).
-template <typename T, int KA, typename X>
+template <typename T, int KA, typename X, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                      const double* __restrict__ part, int32_t nblk, int64_t n,
                                                      X* __restrict__ x, const T* __restrict__ p,
@@ -354,9 +359,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
                                                      T* __restrict__ r, const T* __restrict__ rh0,
                                                      double* __restrict__ part_out) {
     if (ctl->halt) return;
-    __shared__ double lds[kKp * kMaxWaves];
+    __shared__ double lds[2 * kKp * kMaxWaves];
     double red[KA];
-    reduce_partials<KA>(part, nblk, red, lds);
+    reduce_partials_kh<KA, KH>(part, nblk, red, lds);
     rsc_all(sc, red);
     const int cur = it & 1;
     double om[3], al[3];
@@ -380,8 +385,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
         }
     }
     double acc[kKp];
+    float cmp[kKp];
 #pragma unroll
-    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kKp; ++k) {
+        acc[k] = 0.0;
+        cmp[k] = 0.f;
+    }
     const T A[3] = {(T)al[0], (T)al[1], (T)al[2]};
     const T W[3] = {(T)om[0], (T)om[1], (T)om[2]};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
@@ -405,20 +414,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_close(Ctl* __restrict__ ctl, int3
                 xo[c] = t + om[c] * (double)ss[c];
             }
             ro[c] = ss[c] - W[c] * aa[c];
-            acc[c] += (double)hh[c] * (double)ro[c];
-            acc[3 + c] += (double)ro[c] * (double)ro[c];
+            dot_add<KH>(acc[c], cmp[c], (double)hh[c], (double)ro[c]);
+            dot_add<KH>(acc[3 + c], cmp[3 + c], (double)ro[c], (double)ro[c]);
         }
         st3(x, i, V3<X>{xo[0], xo[1], xo[2]});
         st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
     }
-    write_partials<kKp>(acc, lds, part_out);
+    write_partials_kh<kKp, KH>(acc, cmp, lds, part_out);
 }
 
 // CG close-out: alpha = rho / <p, A p>_D (0, and the component stalled,
 // when that is zero or not finite); x = x + alpha p; r = r - alpha A p;
 // partials (kKp per block) of <r, r>_D, r . r and three zeros, the layout
 // the p update reads.  rho_i is stored as gam[it & 1] for the next beta.
-template <typename T, typename X>
+template <typename T, typename X, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, int32_t it, SolveConst sc,
                                                         const double* __restrict__ part_rho, int32_t nrho,
                                                         const double* __restrict__ part_pap, int32_t npap,
@@ -427,10 +436,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, i
                                                         const double* __restrict__ dw,
                                                         double* __restrict__ part_out) {
     if (ctl->halt) return;
-    __shared__ double lds[kKp * kMaxWaves];
+    __shared__ double lds[2 * kKp * kMaxWaves];
     double rho[3], pap[3];
-    reduce_partials<3>(part_rho, nrho, rho, lds);
-    reduce_partials<3>(part_pap, npap, pap, lds);
+    reduce_partials_kh<3, KH>(part_rho, nrho, rho, lds);
+    reduce_partials_kh<3, KH>(part_pap, npap, pap, lds);
     rsc_all(sc, rho);
     rsc_all(sc, pap);
     const int cur = it & 1;
@@ -458,8 +467,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, i
         }
     }
     double acc[kKp];
+    float cmp[kKp];
 #pragma unroll
-    for (int k = 0; k < kKp; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kKp; ++k) {
+        acc[k] = 0.0;
+        cmp[k] = 0.f;
+    }
     const T A[3] = {(T)al[0], (T)al[1], (T)al[2]};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
@@ -477,13 +490,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_cg_close(Ctl* __restrict__ ctl, i
             if constexpr (sizeof(X) == sizeof(T)) xo[c] = xx[c] + A[c] * pp[c];
             else xo[c] = (double)xx[c] + al[c] * (double)pp[c];
             ro[c] = rr[c] - A[c] * aa[c];
-            acc[c] += d * (double)ro[c] * (double)ro[c];
-            acc[3 + c] += (double)ro[c] * (double)ro[c];
+            dot_add_w<KH>(acc[c], cmp[c], d, (double)ro[c], (double)ro[c]);
+            dot_add<KH>(acc[3 + c], cmp[3 + c], (double)ro[c], (double)ro[c]);
         }
         st3(x, i, V3<X>{xo[0], xo[1], xo[2]});
         st3(r, i, V3<T>{ro[0], ro[1], ro[2]});
     }
-    write_partials<kKp>(acc, lds, part_out);
+    write_partials_kh<kKp, KH>(acc, cmp, lds, part_out);
 }
 
 // CG start: wall rows (identity rows of the dynamic-wall system) take their
@@ -530,14 +543,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_check_decide(Ctl* __restrict__ ct
 
 // Step 3: r = r0hat = r_true for restarted components, and partials of the
 // new r0hat . r, r . r.
-template <typename T>
+template <typename T, bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_check_copy(const Ctl* __restrict__ ctl, int64_t n,
                                                           const T* __restrict__ rt, T* __restrict__ r,
                                                           T* __restrict__ rh0, double* __restrict__ part) {
-    __shared__ double lds[6 * kMaxWaves];
+    __shared__ double lds[2 * 6 * kMaxWaves];
     double acc[6];
+    float cmp[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        acc[k] = 0.0;
+        cmp[k] = 0.f;
+    }
     const int rs[3] = {ctl->restart[0], ctl->restart[1], ctl->restart[2]};
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int64_t rpb = ceil_div(n, (int64_t)gridDim.x);
@@ -553,19 +570,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_check_copy(const Ctl* __restrict_
             st3(rh0, i, hv);
             const double q[3] = {(double)rv.x, (double)rv.y, (double)rv.z};
             for (int c = 0; c < 3; ++c) {
-                acc[c] += q[c] * q[c];
-                acc[3 + c] += q[c] * q[c];
+                dot_add<KH>(acc[c], cmp[c], q[c], q[c]);
+                dot_add<KH>(acc[3 + c], cmp[3 + c], q[c], q[c]);
             }
         }
     }
-    write_partials<6>(acc, lds, part);
+    write_partials_kh<6, KH>(acc, cmp, lds, part);
 }
 
+template <bool KH = false>
 __global__ __launch_bounds__(kMaxBlock) void k_check_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
                                                             int32_t nblk, SolveConst sc) {
-    __shared__ double lds[6 * kMaxWaves];
+    __shared__ double lds[2 * 6 * kMaxWaves];
     double red[6];
-    reduce_partials<6>(part, nblk, red, lds);
+    reduce_partials_kh<6, KH>(part, nblk, red, lds);
     rsc_all(sc, red);
     if (threadIdx.x != 0) return;
     for (int c = 0; c < 3; ++c) {
@@ -629,8 +647,10 @@ sph_status read_ctl(sph_ctx* ctx, const Ctl* d, Ctl* h) {
 
 // T: precision of the operator and of the Krylov vectors; X: precision of
 // the solution and of the caller's arrays (X = T, or FP64 under an FP32
-// operator).
-template <typename T, typename X>
+// operator).  KH: the paper's single-precision arithmetic (T = X = float):
+// compensated FP32 inner products and gemv over the FP32 matrix of
+// cell-relative positions (the true residual stays FP64).
+template <typename T, typename X, bool KH = false>
 struct Solver {
     sph_ctx* ctx;
     const sph_nbr* nb;
@@ -680,8 +700,8 @@ struct Solver {
     void apply(const int32_t* halt, const XT* xin, T* yout, const T* w, double* part) {
         const double* aux = MODE == kDotCG ? dw : b64;
         if (mode == SPH_OP_CACHED)
-            hipLaunchKernelGGL((k_apply_sell<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, L.n, sell, xin, yout,
-                               w, aux, part);
+            hipLaunchKernelGGL((k_apply_sell<T, MODE, XT, KH && MODE != kDotResid>), ga(), ba(), 0, ctx->stream,
+                               halt, L.n, sell, xin, yout, w, aux, part);
         else
             hipLaunchKernelGGL((k_apply_otf<T, MODE, XT>), ga(), ba(), 0, ctx->stream, halt, nb->view(), pv, op,
                                xin, yout, w, aux, part);
@@ -704,13 +724,13 @@ struct Solver {
     // rotated CG: P (p and the partials of rho), A (A p, <p, A p>_D), K
     sph_status iteration_cg(int32_t it) {
         const int32_t* halt = &ctl->halt;
-        hipLaunchKernelGGL(k_pupd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
+        hipLaunchKernelGGL((k_pupd<T, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
                            (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist, dw, pa2);
         hipEvent_t ev1 = nullptr;
         SPH_TRY(time_begin(it, &ev1));
         apply<kDotCG>(halt, p, ap, nullptr, pa1);
         if (ev1) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-        hipLaunchKernelGGL((k_cg_close<T, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, (const double*)pa2,
+        hipLaunchKernelGGL((k_cg_close<T, X, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, (const double*)pa2,
                            L.grid_stream, (const double*)pa1, L.grid_apply, L.n, x, p, ap, r, dw, pk3);
         launches += 2;
         if (sc.true_res_period > 0 && it % sc.true_res_period == 0) true_residual(halt, ptr);
@@ -720,24 +740,25 @@ struct Solver {
     sph_status iteration(int32_t it) {
         if (sc.variant == SPH_CG) return iteration_cg(it);
         const int32_t* halt = &ctl->halt;
-        hipLaunchKernelGGL(k_pupd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
+        hipLaunchKernelGGL((k_pupd<T, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pk3, L.grid_stream,
                            (const double*)ptr, L.n, r, rh0, p, ap, tmp, hist, stallhist, (const double*)nullptr,
                            (double*)nullptr);
         apply<kDotA1>(halt, p, ap, rh0, pa1);
-        hipLaunchKernelGGL(k_supd<T>, gs(), bs(), 0, ctx->stream, ctl, it, sc, pa1, L.grid_apply, L.n, r, ap, s);
+        hipLaunchKernelGGL((k_supd<T, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa1, L.grid_apply, L.n, r, ap,
+                           s);
         hipEvent_t ev1 = nullptr;
         SPH_TRY(time_begin(it, &ev1));
         const bool timed = ev1 != nullptr;
         if (sc.variant == SPH_STANDARD) {
             apply<kDotA2Std>(halt, s, as, nullptr, pa2);
             if (timed) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 9, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
-                               p, s, as, r, rh0, pk3);
+            hipLaunchKernelGGL((k_close<T, 9, X, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply,
+                               L.n, x, p, s, as, r, rh0, pk3);
         } else {
             apply<kDotA2>(halt, s, as, nullptr, pa2);
             if (timed) SPH_HIP(hipEventRecord(ev1, ctx->stream));
-            hipLaunchKernelGGL((k_close<T, 6, X>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply, L.n, x,
-                               p, s, as, r, rh0, pk3);
+            hipLaunchKernelGGL((k_close<T, 6, X, KH>), gs(), bs(), 0, ctx->stream, ctl, it, sc, pa2, L.grid_apply,
+                               L.n, x, p, s, as, r, rh0, pk3);
         }
         launches += 3;
         // the next p update applies the periodic FP64 residual check
@@ -751,23 +772,25 @@ struct Solver {
     void host_check() {
         true_residual(nullptr, pchk);
         hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl, pchk, L.grid_apply, sc);
-        hipLaunchKernelGGL(k_check_copy<T>, gs(), bs(), 0, ctx->stream, ctl, L.n, tmp, r, rh0,
+        hipLaunchKernelGGL((k_check_copy<T, KH>), gs(), bs(), 0, ctx->stream, ctl, L.n, tmp, r, rh0,
                            pchk + 3 * (size_t)L.grid_apply);
-        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl,
+        hipLaunchKernelGGL(k_check_finish<KH>, dim3(1), dim3(kMaxBlock), 0, ctx->stream, ctl,
                            pchk + 3 * (size_t)L.grid_apply, L.grid_stream, sc);
         launches += 3;
     }
 };
 
-template <typename T, typename X>
+template <typename T, typename X, bool KH = false>
 sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part, const sph_visc_params* vp,
                       int32_t prec, const void* const rhs[3], void* const xout[3], const sph_solve_opts* o,
                       sph_solve_report* rep) {
-    Solver<T, X> S;
+    Solver<T, X, KH> S;
     S.ctx = ctx;
     S.nb = nb;
-    S.mode = vp->op_mode;
+    // the paper's single precision keeps its FP32 matrix like the cached operator
+    S.mode = vp->op_mode == SPH_OP_PAPER32 ? SPH_OP_CACHED : vp->op_mode;
     S.op = OpParams{vp->dt, vp->wall, vp->avg, vp->jacobi ? 1 : 0};
+    S.op.f32cell = KH ? 1 : 0;
     const int64_t n = nb->n;
     S.L = make_launch(n);
     const Launch& L = S.L;
@@ -807,7 +830,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     SPH_TRY(ctx->ensure_t(kHist, (size_t)hist_rows * 3, &S.hist));
     SPH_TRY(ctx->ensure_t(kStallHist, (size_t)hist_rows * 3, &S.stallhist));
 
-    S.sc.fp32 = o->fp32_scalars ? 1 : 0;
+    S.sc.fp32 = (o->fp32_scalars || KH) ? 1 : 0;
     if (S.sc.fp32) {
         const float tf = (float)o->tol;
         S.sc.tol2 = (double)(tf * tf);
@@ -899,7 +922,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     }
     SPH_HIP(hipMemsetAsync(S.p, 0, sizeof(T) * v3, ctx->stream));
     SPH_HIP(hipMemsetAsync(S.ap, 0, sizeof(T) * v3, ctx->stream));
-    hipLaunchKernelGGL(k_init<T>, S.gs(), S.bs(), 0, ctx->stream, n, S.b, r0, S.r, S.rh0, S.pk3);
+    hipLaunchKernelGGL((k_init<T, KH>), S.gs(), S.bs(), 0, ctx->stream, n, S.b, r0, S.r, S.rh0, S.pk3);
     ++S.launches;
     SPH_LAUNCHED("solve setup");
     SPH_HIP(hipEventRecord(e1, ctx->stream));
@@ -1052,6 +1075,7 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
         return ctx->fail(SPH_E_ARG, "visc_solve: variant");
     if (opts->fp32_scalars && prec != SPH_F32)
         return ctx->fail(SPH_E_ARG, "visc_solve: fp32_scalars needs prec = SPH_F32");
+
     if (opts->variant == SPH_CG && params && params->wall == SPH_WALL_DUMMY)
         return ctx->fail(SPH_E_ARG, "visc_solve: the CG needs a symmetric system (dynamic walls)");
     if (opts->true_res_period < 0) return ctx->fail(SPH_E_ARG, "visc_solve: true_res_period < 0");
@@ -1065,6 +1089,8 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
     sph_status st = check_particles(ctx, nb, p);
     // SPH_MIXED: FP32 operator and vectors (checked as SPH_F32), FP64 solution
     if (st == SPH_OK) st = check_params(ctx, params, prec == SPH_MIXED ? SPH_F32 : prec);
+    if (st == SPH_OK && params->op_mode == SPH_OP_PAPER32 && prec != SPH_F32)
+        st = ctx->fail(SPH_E_ARG, "visc_solve: SPH_OP_PAPER32 is single precision (SPH_F32)");
     if (st == SPH_OK) {
         double* hist_keep = report->history;
         int32_t cap_keep = report->history_cap;
@@ -1073,6 +1099,10 @@ extern "C" sph_status sph_visc_solve(sph_ctx* ctx, const sph_nbr* nb, const sph_
         report->history_cap = cap_keep;
         if (prec == SPH_F64)
             st = solve_impl<double, double>(ctx, nb, p, params, prec, rhs, x, opts, report);
+        else if (params->op_mode == SPH_OP_PAPER32 && nb->g.kernel != SPH_KERNEL_WENDLAND)
+            st = ctx->fail(SPH_E_ARG, "visc_solve: SPH_OP_PAPER32 is defined for the Wendland kernel");
+        else if (params->op_mode == SPH_OP_PAPER32)
+            st = solve_impl<float, float, true>(ctx, nb, p, params, prec, rhs, x, opts, report);
         else if (prec == SPH_F32)
             st = solve_impl<float, float>(ctx, nb, p, params, prec, rhs, x, opts, report);
         else

@@ -160,6 +160,73 @@ __device__ inline double pair_W(const Grid& g, double r2) {
 }
 
 // ---------------------------------------------------------------------------
+// Single-precision pair data from cell-relative positions (appendix on
+// relative positions): each particle's position is held as its FP32 offset
+// r' from the centre of its cell, and the displacement of a pair is
+// o' + (r'_b - r'_a) with o' = l (c_b - c_a) the FP32 offset of the two cell
+// centres (the grouping that rounds the same way for (b, a) and (a, b), so
+// the matrix stays numerically symmetric where it should).  The cell offset
+// is the minimum image: on periodic axes the integer cell difference takes
+// the period multiple that the FP64 displacement of the neighbour search
+// takes.
+// ---------------------------------------------------------------------------
+__device__ inline int32_t cell_coord(const Grid& g, int32_t c, int axis) {
+    if (axis == 0) return c % g.nc[0];
+    if (axis == 1) return (c / g.nc[0]) % g.nc[1];
+    return c / (g.nc[0] * g.nc[1]);
+}
+// FP32 offset of coordinate x from the centre of cell index ci on an axis.
+__device__ inline float rel_pos(const Grid& g, int axis, double x, int32_t ci) {
+    const double centre = g.org[axis] + ((double)ci + 0.5) * g.cs[axis];
+    return (float)disp(x, centre, g.period[axis]);
+}
+// FP32 squared distance of sorted particles b and a from cell-relative data.
+__device__ inline float dist2_f32(const Grid& g, const Pos4& pb, int32_t cb, const Pos4& pa, int32_t ca) {
+    const double xb[3] = {pb.x, pb.y, pb.z}, xa[3] = {pa.x, pa.y, pa.z};
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int32_t ib = cell_coord(g, cb, k), ia = cell_coord(g, ca, k);
+        const float rb = rel_pos(g, k, xb[k], ib), ra = rel_pos(g, k, xa[k], ia);
+        int64_t dc = (int64_t)ib - ia;
+        if (g.period[k] > 0.0) {
+            const double d64 = disp(xb[k], xa[k], g.period[k]);
+            const double rest = d64 - (double)dc * g.cs[k] - ((double)rb - (double)ra);
+            dc += (int64_t)rint(rest / g.period[k]) * g.nc[k];
+        }
+        const float o = (float)g.cs[k] * (float)dc;
+        d[k] = o + (rb - ra);
+    }
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+// Wendland F(r) = f(r/h)/h^5 and W(r) = w(r/h)/h^3 in FP32.
+__device__ inline float wendland_F_f32(const Grid& g, float r2) {
+    const float q = sqrtf(r2) / (float)g.h;
+    if (!(q < 2.0f)) return 0.0f;
+    const float a = q - 2.0f;
+    return ((float)(105.0 / (128.0 * kPi)) * ((a * a) * a)) * (float)g.inv_h5;
+}
+__device__ inline float wendland_W_f32(const Grid& g, float r2) {
+    const float q = sqrtf(r2) / (float)g.h;
+    if (!(q < 2.0f)) return 0.0f;
+    const float a = 1.0f - 0.5f * q;
+    return (((float)(21.0 / (16.0 * kPi)) * (((a * a) * a) * a)) * (2.0f * q + 1.0f)) * (float)g.inv_h3;
+}
+// Pair weight of eq. kab in FP32: -(2 mubar m_a / rho_a) F / rho_b.
+__device__ inline float pair_w_f32(const Grid& g, int avg, float mu_a, float m_a, float rho_a, float mu_b,
+                                   float rho_b, float r2) {
+    float tm;
+    if (avg == SPH_AVG_HARMONIC) {
+        const float s = mu_a + mu_b;
+        tm = s > 0.0f ? (4.0f * (mu_a * mu_b)) / s : 0.0f;
+    } else {
+        tm = mu_a + mu_b;
+    }
+    const float F = wendland_F_f32(g, r2);
+    return -((tm * (m_a / rho_a)) * F) / rho_b;
+}
+
+// ---------------------------------------------------------------------------
 // Interleaved 3-vectors (x, y, z of one particle adjacent in memory).
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -245,6 +312,138 @@ __device__ inline void write_partials(double (&v)[K], double* lds, double* __res
 }
 
 __device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// Compensated single-precision sums: the paper's arithmetic for every
+// multi-term sum in single precision (Kahan's summation; appendix
+// "Implementation notes").  A running sum is the pair (s, c): s the FP32
+// sum, c Kahan's compensation (the rounding error of the last addition,
+// subtracted from the next term).  Each lane sums its own terms in order;
+// lanes, waves and blocks are merged by adding the other sum's s and then
+// its -c the same way, in a fixed order.  Every block's merged sum s is its
+// partial; the next kernel's blocks sum the partials again with Kahan's
+// compensation, thread by thread in block order, then merge.
+// ---------------------------------------------------------------------------
+__device__ inline void kahan_add(float& s, float& c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+__device__ inline void kahan_merge(float& s, float& c, float s2, float c2) {
+    kahan_add(s, c, s2);
+    kahan_add(s, c, -c2);
+}
+
+// One term of an inner product: acc += a b in FP64 (KH false) or the FP32
+// product of a and b added with compensation (KH true: acc holds the FP32
+// sum exactly, comp its compensation).
+template <bool KH>
+__device__ inline void dot_add(double& acc, float& comp, double a, double b) {
+    if constexpr (!KH) {
+        acc += a * b;
+    } else {
+        float s = (float)acc;
+        kahan_add(s, comp, (float)a * (float)b);
+        acc = (double)s;
+    }
+}
+// (w a) b with each product rounded to FP32 under KH.
+template <bool KH>
+__device__ inline void dot_add_w(double& acc, float& comp, double w, double a, double b) {
+    if constexpr (!KH) {
+        acc += w * a * b;
+    } else {
+        float s = (float)acc;
+        kahan_add(s, comp, ((float)w * (float)a) * (float)b);
+        acc = (double)s;
+    }
+}
+
+// Block-wide compensated merge of K per-thread sums; result (FP32 values)
+// valid in every thread.  `lds` must hold 2 K kMaxWaves doubles.
+template <int K>
+__device__ inline void block_sum_kahan(double (&v)[K], float (&cmp)[K], double* lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    float s[K], c[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s[k] = (float)v[k];
+        c[k] = cmp[k];
+    }
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float s2 = __shfl_xor(s[k], off, kWave);
+            const float c2 = __shfl_xor(c[k], off, kWave);
+            // the lower lane of each pair keeps its own sum first, so both
+            // lanes form the same merged value
+            if (lane & off) {
+                float a = s2, b = c2;
+                kahan_merge(a, b, s[k], c[k]);
+                s[k] = a;
+                c[k] = b;
+            } else {
+                kahan_merge(s[k], c[k], s2, c2);
+            }
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            lds[(2 * k) * kMaxWaves + wid] = (double)s[k];
+            lds[(2 * k + 1) * kMaxWaves + wid] = (double)c[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float a = 0.f, b = 0.f;
+        for (int w = 0; w < nw; ++w)
+            kahan_merge(a, b, (float)lds[(2 * k) * kMaxWaves + w], (float)lds[(2 * k + 1) * kMaxWaves + w]);
+        v[k] = (double)a;
+        cmp[k] = b;
+    }
+    __syncthreads();
+}
+
+// Partials of the block: FP64 sums (KH false) or merged Kahan sums.
+template <int K, bool KH>
+__device__ inline void write_partials_kh(double (&v)[K], float (&cmp)[K], double* lds,
+                                         double* __restrict__ part) {
+    if constexpr (!KH) {
+        write_partials<K>(v, lds, part);
+    } else {
+        block_sum_kahan<K>(v, cmp, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) part[(int64_t)blockIdx.x * K + k] = v[k];
+        }
+    }
+}
+
+// reduce_partials, or (KH) the compensated FP32 sum of the partials.
+template <int K, bool KH>
+__device__ inline void reduce_partials_kh(const double* __restrict__ part, int nblk, double (&out)[K],
+                                          double* lds) {
+    if constexpr (!KH) {
+        reduce_partials<K>(part, nblk, out, lds);
+    } else {
+        float cmp[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            float s = 0.f, c = 0.f;
+            for (int b = threadIdx.x; b < nblk; b += blockDim.x) kahan_add(s, c, (float)part[(int64_t)b * K + k]);
+            out[k] = (double)s;
+            cmp[k] = c;
+        }
+        block_sum_kahan<K>(out, cmp, lds);
+    }
+}
 
 // XCD-aware block order: the hardware hands consecutive block ids to the 8
 // XCDs in turn; remap so that each XCD works on one contiguous share of the

@@ -69,6 +69,11 @@ struct OpParams {
     int32_t wall;
     int32_t avg;
     int32_t jacobi;
+    // 1: the paper's single-precision matrix (cached operator only): pair
+    // weights evaluated in FP32 from cell-relative FP32 positions, FP32
+    // diagonal and wall normalisation by compensated sums; the matrix keeps
+    // the plain diagonal per row in place of the row sum
+    int32_t f32cell = 0;
 };
 
 // Sliced ELLPACK matrix, one slice = 64 consecutive rows (one wavefront).

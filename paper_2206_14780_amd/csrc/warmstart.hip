@@ -426,7 +426,8 @@ sph_status prepare(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* p, cons
     w->nb = nb;
     SPH_TRY(gather_props(ctx, nb, p, &w->pv));
     w->op = OpParams{v->dt, v->wall, v->avg, v->jacobi ? 1 : 0};
-    w->mode = v->op_mode;
+    w->op.f32cell = v->op_mode == SPH_OP_PAPER32 ? 1 : 0;
+    w->mode = v->op_mode == SPH_OP_PAPER32 ? SPH_OP_CACHED : v->op_mode;
     w->sell = sell;
     if (w->mode == SPH_OP_CACHED)
         SPH_TRY(build_sell<T>(ctx, nb, w->pv, w->op, sell, &w->diag64));

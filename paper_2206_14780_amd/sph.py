@@ -24,7 +24,7 @@ SPH_WALL_DYNAMIC, SPH_WALL_DUMMY = 0, 1
 SPH_AVG_ARITH, SPH_AVG_HARMONIC = 0, 1
 SPH_ROBUST, SPH_STANDARD, SPH_CG = 0, 1, 2
 SPH_KERNEL_WENDLAND, SPH_KERNEL_GAUSSIAN = 0, 1
-SPH_OP_CACHED, SPH_OP_ONTHEFLY = 0, 1
+SPH_OP_CACHED, SPH_OP_ONTHEFLY, SPH_OP_PAPER32 = 0, 1, 2
 SPH_CONVERGED, SPH_STATE_STALLED, SPH_PROGRESSING = 0, 1, 2
 SPH_MLP_NPARAM, SPH_MLP_SAMPLE = 8835, 8
 SPH_NOALLOC_MAX_N = 262144

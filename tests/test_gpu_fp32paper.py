@@ -155,3 +155,88 @@ def test_fp32_scalars_edge_cases(ctx):
     a, ra = gt.solve(t.rhs, S.SPH_F32, tol=1e-6, **PAPER)
     b, rb = gt.solve(t.rhs, S.SPH_F32, tol=1e-6, **PAPER)
     assert np.array_equal(a, b) and ra["history"] == rb["history"]
+
+
+# --- the paper's single-precision arithmetic throughout (SPH_OP_PAPER32): FP32
+# matrix from cell-relative positions, compensated gemv, compensated inner
+# products, FP32 scalars -------------------------------------------------------
+
+PAPER32 = dict(true_res_period=0, restart_drop=0.0, op_mode=S.SPH_OP_PAPER32)
+U32 = 2.0 ** -24
+
+
+def _paper32(w, jacobi=True):
+    return OF.Paper32Operator(oracle_op(w, jacobi=jacobi), w.lo, w.hi, w.periodic)
+
+
+@pytest.mark.parametrize("jacobi", [True, False])
+@pytest.mark.parametrize("wall", [W.WALL_DUMMY, W.WALL_DYNAMIC])
+def test_paper32_operator_matches_the_oracle(ctx, wall, jacobi):
+    for seed, n in ((41, (6, 6, 5)), (43, (9, 7, 6))):
+        w = small_tank(seed=seed, n=n, wall=wall, mu_span=1000.0, dt_nu=50.0)
+        print(f"[paper32 apply] {w.name} n={w.n} wall={wall} jacobi={jacobi}", flush=True)
+        g = GpuCase(ctx, w)
+        X = np.random.default_rng(seed).normal(size=(w.n, 3)).astype(np.float32)
+        Yg = g.apply(X.astype(np.float64), S.SPH_F32, jacobi=jacobi, op_mode=S.SPH_OP_PAPER32)
+        P = _paper32(w, jacobi)
+        Yo = P.apply(X).astype(np.float64)
+        rows = np.repeat(np.arange(w.n), np.diff(P.row_ptr))
+        Xd = X.astype(np.float64)
+        mag = np.abs(P.diag.astype(np.float64))[:, None] * np.abs(Xd)
+        np.add.at(mag, rows, np.abs(P.off.astype(np.float64))[:, None] * np.abs(Xd[P.cols]))
+        # both sides: FP32 products, Kahan sums (4u each), entries equal up to
+        # the summation order of the diagonal (a few units in the last place)
+        assert np.all(np.abs(Yg - Yo) <= 16 * U32 * mag + 1e-37), (w.name, np.abs(Yg - Yo).max())
+        # and the operator is the FP64 one to FP32 accuracy
+        Yd = oracle_op(w, jacobi=jacobi).apply(Xd)
+        assert np.all(np.abs(Yg - Yd) <= 128 * U32 * mag + 1e-37)
+
+
+@pytest.mark.parametrize("variant", [S.SPH_ROBUST, S.SPH_STANDARD])
+@pytest.mark.parametrize("wall", [W.WALL_DUMMY, W.WALL_DYNAMIC])
+def test_paper32_solve_matches_the_oracle(ctx, variant, wall):
+    w = small_tank(seed=31, wall=wall, mu_span=100.0, dt_nu=10.0)
+    print(f"[paper32 solve] {w.name} variant={variant} wall={wall}", flush=True)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F32, tol=1e-6, variant=variant, **PAPER32)
+    op = oracle_op(w)
+    Xo, ro, ho = OF.solve(op, w.rhs, tol=1e-6, variant=variant, dots="kahan", paper32=_paper32(w))
+    print(f"[paper32 solve] iterations GPU {rep['iters']} oracle {ro['iters']}", flush=True)
+    assert rep["status"] == 0 and ro["state"] == [O.CONVERGED] * 3
+    assert abs(rep["iters"] - ro["iters"]) <= max(2, ro["iters"] // 5)
+    assert _is_f32(rep["rr"]) and _is_f32(rep["tau2"]) and _is_f32(rep["history"])
+    assert np.allclose(rep["tau2"], ro["tau2"], rtol=2.0 ** -21, atol=0)
+    h = np.asarray(rep["history"])[:4]
+    assert np.all(np.abs(h / ho[:4] - 1.0) < 1e-3)
+    Xd, _, _ = O.solve(op, w.rhs, tol=1e-12)
+    assert rel_l2(X, Xd) < 2e-5 and rel_l2(Xo, Xd) < 2e-5
+
+
+def test_paper32_refused_outside_its_definition(ctx):
+    w = small_tank(seed=35)
+    g = GpuCase(ctx, w)
+    for prec in (S.SPH_F64, S.SPH_MIXED):
+        with pytest.raises(S.SphError) as e:
+            g.solve(w.rhs, prec, **PAPER32)
+        assert e.value.status == S.SPH_E_ARG
+    import dataclasses
+    wg = dataclasses.replace(w, kernel=W.KERNEL_GAUSSIAN)
+    gg = GpuCase(ctx, wg)
+    with pytest.raises(S.SphError) as e:
+        gg.solve(wg.rhs, S.SPH_F32, **PAPER32)
+    assert e.value.status == S.SPH_E_ARG
+
+
+@pytest.mark.parametrize("variant", [S.SPH_ROBUST, S.SPH_STANDARD])
+def test_paper32_tank_100(ctx, variant):
+    # the benchmark tank in the paper's arithmetic from the previous-step
+    # start: converged (the library's closing FP64 true residual meets 1e-6)
+    w = W.open_box(100)
+    g = GpuCase(ctx, w)
+    X, rep = g.solve(w.rhs, S.SPH_F32, X0=w.x0, tol=1e-6, variant=variant, history=False, max_iter=3000,
+                     **PAPER32)
+    rel = [np.sqrt(t / b) for t, b in zip(rep["true_rr"], rep["bb"])]
+    print(f"[paper32 tank] variant={variant} iters {rep['iters']} status {rep['status']} stalls "
+          f"{rep['stall_count']} true rel res {rel}", flush=True)
+    assert rep["status"] in (S.SPH_OK, S.SPH_STALLED)
+    assert _is_f32(rep["rr"])

@@ -194,3 +194,91 @@ def test_kahan_form_cg():
     assert rep["state"] == [O.CONVERGED] * 3
     Xd = O.dense_solve(op, B)
     assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 2e-5
+
+
+# --- the paper's single-precision matrix (appendix on relative positions) ---
+
+def _paper_case(seed=7, uniform=False, wall=W.WALL_DUMMY, jacobi=True, **kw):
+    k, pt = _tank(seed=seed, uniform=uniform, wall=wall, **kw)
+    op = O.Operator(jacobi=jacobi, **k)
+    lo = np.array([0.0, 0.0, -3.0])
+    hi = np.array([6.0, 6.0, 8.0])
+    return op, OF.Paper32Operator(op, lo, hi, [1, 1, 0]), pt, lo, hi
+
+
+def test_cell_relative_positions_rebuild_the_positions():
+    op, P, pt, lo, hi = _paper_case()
+    nc, cs, period = OF.cell_grid(lo, hi, [1, 1, 0], op.h)
+    assert np.all(cs >= 2.0 * op.h) and np.all(nc >= 1)
+    pos = np.stack([op._x, op._y, op._z], axis=1)
+    centre = lo + (P.cell + 0.5) * cs
+    back = centre + P.rel.astype(np.float64)
+    for a in range(3):
+        d = back[:, a] - pos[:, a]
+        if period[a] > 0:
+            d = d - period[a] * np.rint(d / period[a])
+        # the offset is the FP32 rounding of the exact one (|r'| <= a cell)
+        assert np.all(np.abs(d) <= 2.0 ** -24 * cs[a])
+    inside = (pos[:, 2] >= lo[2]) & (pos[:, 2] < hi[2])
+    assert np.all(np.abs(P.rel[inside]) <= 0.5 * cs * (1 + 1e-6))
+
+
+def test_grouped_displacement_gives_a_symmetric_fp32_matrix():
+    # uniform mass, density and viscosity, no scaling: the fluid block is
+    # symmetric, and with the displacement grouped as o' + (r'_b - r'_a) the
+    # FP32 entries are equal bit for bit for (b, a) and (a, b)
+    op, P, pt, _, _ = _paper_case(uniform=True, jacobi=False)
+    n = op.n
+    rows = np.repeat(np.arange(n), np.diff(P.row_ptr))
+    fl = pt == W.FLUID
+    ff = fl[rows] & fl[P.cols]
+    M = {}
+    for b, a, v in zip(rows[ff], P.cols[ff], P.off[ff]):
+        M[(b, a)] = v
+    assert len(M) > 1000
+    assert all(M[(a, b)] == v for (b, a), v in M.items())
+
+
+@pytest.mark.parametrize("wall", [W.WALL_DYNAMIC, W.WALL_DUMMY])
+@pytest.mark.parametrize("jacobi", [True, False])
+def test_fp32_entries_round_the_fp64_matrix(wall, jacobi):
+    op, P, pt, _, _ = _paper_case(wall=wall, jacobi=jacobi, mu_span=100.0, dt_nu=20.0)
+    d64, e64 = op.entries()
+    u = 2.0 ** -24
+    rows = np.repeat(np.arange(op.n), np.diff(P.row_ptr))
+    rowmax = np.zeros(op.n)
+    np.maximum.at(rowmax, rows, np.abs(e64))
+    # each entry is ~15 FP32 operations from the particle data; (q - 2)^3
+    # loses relative accuracy near the support edge, so the bound is on the
+    # row's largest entry
+    assert np.all(np.abs(P.off.astype(np.float64) - e64) <= 64 * u * rowmax[rows] + 1e-45)
+    assert np.allclose(P.diag.astype(np.float64), d64, rtol=8 * u, atol=0)
+    D64 = op.diag()
+    assert np.allclose(P.D.astype(np.float64), D64, rtol=8 * u * 100, atol=0)
+
+
+def test_kahan_gemv_within_its_bound():
+    op, P, pt, _, _ = _paper_case(mu_span=1000.0, dt_nu=50.0)
+    X = np.random.default_rng(4).normal(size=(op.n, 3)).astype(np.float32)
+    Y = P.apply(X)
+    # the same FP32 matrix applied in exact-enough FP64 arithmetic
+    rows = np.repeat(np.arange(op.n), np.diff(P.row_ptr))
+    Xd = X.astype(np.float64)
+    Ye = P.diag.astype(np.float64)[:, None] * Xd
+    np.add.at(Ye, rows, P.off.astype(np.float64)[:, None] * Xd[P.cols])
+    mag = np.abs(P.diag.astype(np.float64))[:, None] * np.abs(Xd)
+    np.add.at(mag, rows, np.abs(P.off.astype(np.float64))[:, None] * np.abs(Xd[P.cols]))
+    u = 2.0 ** -24
+    # FP32 rounding of each product (u) plus Kahan's 2u on the sum
+    assert np.all(np.abs(Y.astype(np.float64) - Ye) <= 4 * u * mag + 1e-37)
+
+
+@pytest.mark.parametrize("variant", [O.ROBUST, O.STANDARD])
+def test_paper_single_precision_solve(variant):
+    op, P, pt, _, _ = _paper_case(mu_span=100.0, dt_nu=10.0)
+    B = np.random.default_rng(7).normal(size=(op.n, 3))
+    X, rep, h = OF.solve(op, B, tol=1e-6, variant=variant, dots="kahan", paper32=P)
+    assert X.dtype == np.float32 and h.dtype == np.float32
+    assert rep["state"] == [O.CONVERGED] * 3
+    Xd = O.dense_solve(op, B)
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 2e-5
