@@ -197,6 +197,7 @@ def lava_sequence(ctx, w, leg, warmup, steps, profile_every):
            "time_to_tol_ms_median": round(float(np.median([r["setup_ms"] + r["iterate_ms"] for r in reps])), 3),
            "setup_ms_median": round(float(np.median([r["setup_ms"] for r in reps])), 3),
            "launches_per_iteration": round(sum(r["launches"] for r in reps) / max(sum(iters), 1), 3),
+           "issued_iterations_executed": round(sum(iters) / max(sum(r["issued_iters"] for r in reps), 1), 4),
            "true_rel_res_max": round(max(_rel(r) for r in reps), 9),
            "final_max_vx": round(float(V[0].abs().max()), 6)}
     if warm is not None:
@@ -248,6 +249,8 @@ def tank_leg(ctx, n, steps):
            "particle_iters_per_s": w.n * sum(q["iters"] for q in reps) / total,
            "time_to_tol_ms": round(r["setup_ms"] + r["iterate_ms"], 3), "setup_ms": round(r["setup_ms"], 3),
            "launches_per_iteration": round(r["launches"] / max(r["iters"], 1), 3),
+           "issued_iterations_executed": round(sum(q["iters"] for q in reps) /
+                                               max(sum(q["issued_iters"] for q in reps), 1), 4),
            "true_rel_res": round(_rel(r), 9), "avg_apply_launch_ms": round(a_ms, 4),
            "mat_nnz": int(r["mat_nnz"]), "mat_slots": int(r["mat_slots"])}
     print(f"[bench] tank: {json.dumps(out)}", flush=True)
@@ -620,6 +623,7 @@ def main():
         "iterations": head["iterations"],
         "time_to_tol_ms": head["time_to_tol_ms_median"],
         "launches_per_iteration": head["launches_per_iteration"],
+        "issued_iterations_executed": head["issued_iterations_executed"],
         "true_rel_res_max": head["true_rel_res_max"],
         "roofline": roofline,
         "sequence": seq,

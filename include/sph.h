@@ -151,8 +151,11 @@ typedef struct {
  *          on-the-fly operator; a converged component that fails it is
  *          restarted from that residual.  0 = only when no component progresses.
  *   x0_given: 1 = x holds the initial guess on entry, 0 = start from zero.
- *   poll_every: iterations issued between two host reads of the device stop
- *          flag (0 = library default).  Does not change the result.
+ *   poll_every: most iterations issued between two host reads of the device
+ *          control block (0 = library default, 8).  Batches grow 2, 4, ... up
+ *          to it, and shrink to what the residual history predicts is left,
+ *          so that few iterations are issued past the halt.  Does not change
+ *          the result.
  *   force_stall_iter / force_stall_comp: test hook; at that iteration that
  *          component's delta is treated as zero.  -1 = off.
  *   profile: k > 0 = bracket the second operator launch (A r_star and its
@@ -242,6 +245,8 @@ typedef struct {
     double plain_rr[3];     /* true r.r of the plain start */
     double warm_scale;      /* U, the normalisation of the features */
     double warm_ms;         /* device time of forming the learned guess and both residuals */
+    int32_t issued_iters;   /* iterations queued by the host; those past the halt
+                               (issued_iters - iters) return at once */
 } sph_solve_report;
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream`

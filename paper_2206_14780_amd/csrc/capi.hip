@@ -49,7 +49,7 @@ extern "C" sph_status sph_create(sph_ctx** out, int32_t device, void* hip_stream
     sph_ctx* ctx = new sph_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipHostMalloc(&ctx->host_mail, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&ctx->host_mail, sph::kHostMailBytes, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return SPH_E_OOM;
     }

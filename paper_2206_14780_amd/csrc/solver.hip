@@ -22,6 +22,7 @@
 // the control block.  All inner products and scalars are FP64.
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 
 #include "mlp.hpp"
 #include "operator_kernels.hpp"
@@ -670,6 +671,7 @@ struct Solver {
     int32_t* stallhist;
     SolveConst sc;
     int32_t launches = 0;
+    int32_t issued_iters = 0;  // iterations queued over all rounds
     // profiling of the A r_star launches: (iteration, issue round, event pair)
     int32_t profile = 0;  // time the A r_star launch of every profile-th iteration
     int32_t round = 0;
@@ -778,6 +780,92 @@ struct Solver {
                            pchk + 3 * (size_t)L.grid_apply, L.grid_stream, sc);
         launches += 3;
     }
+};
+
+// How many iterations the host queues before its next poll of the control
+// block.  With nothing known the batches grow 2, 4, 8 (up to kmax).  Two
+// polls give each progressing component c a rate of decrease of ln(r.r) per
+// iteration (the steeper of the latest interval's and the round's average,
+// so that a noisy residual history errs towards short batches; a round
+// after a restart starts from the rates of the round before), and from it
+// the iterations m_c left to reach its tolerance.  The iteration whose
+// p-update halts is then predicted at H = iter + max_c m_c (iter: the last
+// p-update polled), and each batch covers half of what is left up to H.
+// When every issued iteration already reaches H the host queues nothing
+// until the next poll is read (unless none is in flight), so a solve that
+// ends as predicted leaves no iteration issued past its halt.  The halting
+// iteration itself is always issued (its p-update decides the halt), once
+// per round of host-side residual checks.
+class IssuePlan {
+  public:
+    explicit IssuePlan(int kmax) : kmax_(kmax) {}
+
+    // a new round after a host-side residual check, whose control block is
+    // `m` (restarted components progressing again from their true r.r): the
+    // residuals start again, the rates are kept
+    void restart(const CtlPoll& m) {
+        k_ = std::min(2, kmax_);
+        npoll_ = 0;
+        have_pred_ = false;
+        observe(m);
+    }
+
+    void observe(const CtlPoll& m) {
+        if (m.halt) return;
+        double lrr[3];
+        for (int c = 0; c < 3; ++c) lrr[c] = m.rr[c] > 0.0 ? std::log(m.rr[c]) : -HUGE_VAL;
+        double horizon = 0.0;
+        bool known = true;
+        for (int c = 0; c < 3; ++c) {
+            if (m.state[c] != SPH_PROGRESSING) continue;
+            if (npoll_ >= 1 && m.iter > it_last_ && m.iter > it_first_ && std::isfinite(lrr[c]) &&
+                std::isfinite(lrr_last_[c]) && std::isfinite(lrr_first_[c])) {
+                const double r_last = (lrr[c] - lrr_last_[c]) / (double)(m.iter - it_last_);
+                const double r_avg = (lrr[c] - lrr_first_[c]) / (double)(m.iter - it_first_);
+                rate_[c] = std::min(r_last, r_avg);
+            }
+            if (!(rate_[c] < 0.0) || !(m.tau2[c] > 0.0) || !std::isfinite(lrr[c])) {
+                known = false;
+                continue;
+            }
+            horizon = std::max(horizon, (std::log(m.tau2[c]) - lrr[c]) / rate_[c]);
+        }
+        if (npoll_ == 0) {
+            it_first_ = m.iter;
+            for (int c = 0; c < 3; ++c) lrr_first_[c] = lrr[c];
+        }
+        it_last_ = m.iter;
+        for (int c = 0; c < 3; ++c) lrr_last_[c] = lrr[c];
+        ++npoll_;
+        have_pred_ = known;
+        if (known) halt_pred_ = m.iter + (int32_t)std::min(std::ceil(horizon), 1.0e6);
+    }
+
+    // iterations to queue now, the first of them being `next`; 0 = wait for
+    // the poll in flight
+    int batch(int32_t next, bool poll_in_flight) {
+        if (!have_pred_) {
+            const int k = k_;
+            k_ = std::min(2 * k_, kmax_);
+            return k;
+        }
+        const int32_t reach = halt_pred_ - next + 1;  // iterations up to H
+        if (reach <= 0) return poll_in_flight ? 0 : 1;
+        // half the distance per batch, so that the polls close in on H; 0
+        // (wait for the poll in flight) once H is the next iteration
+        const int32_t k = poll_in_flight ? reach / 2 : (reach + 1) / 2;
+        return std::min(k, (int32_t)kmax_);
+    }
+
+  private:
+    int kmax_;
+    int k_ = 2;
+    int npoll_ = 0;
+    bool have_pred_ = false;
+    int32_t halt_pred_ = 0;
+    int32_t it_first_ = 0, it_last_ = 0;
+    double lrr_first_[3] = {0.0, 0.0, 0.0}, lrr_last_[3] = {0.0, 0.0, 0.0};
+    double rate_[3] = {0.0, 0.0, 0.0};  // 0: none known yet
 };
 
 template <typename T, typename X, bool KH = false>
@@ -927,43 +1015,54 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     SPH_LAUNCHED("solve setup");
     SPH_HIP(hipEventRecord(e1, ctx->stream));
 
-    // Iterate.  The host issues iterations in batches and reads the device
-    // halt flag one batch behind; kernels issued after a halt return at once.
-    struct Mail {
-        int32_t halt, reason;  // Ctl::halt and Ctl::halt_reason, adjacent
-    };
-    Mail* mail = static_cast<Mail*>(ctx->host_mail);
-    const int kmax = o->poll_every > 0 ? o->poll_every : 8;
+    // Iterate.  The host issues iterations in batches (sized by IssuePlan)
+    // and reads the device's control block one batch behind; kernels issued
+    // after a halt return at once.
+    CtlPoll* mail = static_cast<CtlPoll*>(ctx->host_mail);
+    IssuePlan plan(o->poll_every > 0 ? o->poll_every : 8);
     const int32_t last_it = o->max_iter + 1;  // P of this iteration always halts
     int32_t j = 0;
     Ctl hctl;
     for (;;) {
+        const int32_t j0 = j;
         int32_t it = j + 1;
-        int k = std::min(2, kmax);
+        if (j > 0) {
+            // the round starts after the residual check of iteration j: the
+            // state of the pupd of j + 1, with the true residuals
+            CtlPoll m;
+            std::memcpy(&m, &hctl.rr, sizeof(CtlPoll));
+            for (int c = 0; c < 3; ++c) m.rr[c] = hctl.trr[c];
+            m.iter = j + 1;
+            m.halt = 0;
+            plan.restart(m);
+        }
         int pend[2], npend = 0, batch = 0;
         bool halted = false;
         while (!halted) {
-            if (it <= last_it) {
+            const int k = it <= last_it && npend < 2 ? plan.batch(it, npend > 0) : 0;
+            if (k > 0) {
                 for (int q = 0; q < k && it <= last_it; ++q) SPH_TRY(S.iteration(it++));
                 SPH_LAUNCHED("iteration kernels");
                 const int slot = batch++ & 1;
-                SPH_HIP(hipMemcpyAsync(&mail[slot], &S.ctl->halt, sizeof(Mail), hipMemcpyDeviceToHost,
+                SPH_HIP(hipMemcpyAsync(&mail[slot], &S.ctl->rr, sizeof(CtlPoll), hipMemcpyDeviceToHost,
                                        ctx->stream));
                 SPH_HIP(hipEventRecord(ctx->ev[3 + slot], ctx->stream));
                 pend[npend++] = slot;
-                k = std::min(2 * k, kmax);
             }
-            // read the older poll once two are in flight (or nothing is left to issue)
-            if (npend == 2 || (it > last_it && npend > 0)) {
+            // read the older poll once two are in flight, or when nothing is
+            // to be issued before it
+            if (npend == 2 || (npend > 0 && k == 0)) {
                 const int slot = pend[0];
                 pend[0] = pend[1];
                 --npend;
                 SPH_HIP(hipEventSynchronize(ctx->ev[3 + slot]));
                 if (mail[slot].halt) halted = true;
+                else plan.observe(mail[slot]);
             } else if (it > last_it && npend == 0) {
                 halted = true;
             }
         }
+        S.issued_iters += (it - 1) - j0;
         SPH_TRY(read_ctl(ctx, S.ctl, &hctl));
         if (hctl.nonfinite) return ctx->fail(SPH_E_NONFINITE, "visc_solve: non-finite right-hand side");
         if (!hctl.halt) return ctx->fail(SPH_E_HIP, "visc_solve: iteration issue ended without a halt");
@@ -1028,6 +1127,7 @@ sph_status solve_impl(sph_ctx* ctx, const sph_nbr* nb, const sph_particles* part
     rep->setup_ms = ms_setup;
     rep->iterate_ms = ms_iter;
     rep->launches = S.launches;
+    rep->issued_iters = S.issued_iters;
     if (S.profile > 0) {
         double tot = 0.0;
         int32_t cnt = 0;

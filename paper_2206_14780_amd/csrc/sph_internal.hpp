@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -168,6 +169,24 @@ struct Ctl {
     int32_t n_replaced;
     int32_t nonfinite;
 };
+
+// The fields of Ctl that the host polls between batches of iterations, in
+// one contiguous copy: residuals, tolerances, states, iteration and halt.
+struct CtlPoll {
+    double rr[3];
+    double bb[3];
+    double tau2[3];
+    int32_t state[3];
+    int32_t iter;
+    int32_t halt;
+    int32_t halt_reason;
+};
+static_assert(offsetof(Ctl, halt_reason) + sizeof(int32_t) - offsetof(Ctl, rr) == sizeof(CtlPoll) &&
+                  offsetof(Ctl, state) - offsetof(Ctl, rr) == offsetof(CtlPoll, state) &&
+                  offsetof(Ctl, halt) - offsetof(Ctl, rr) == offsetof(CtlPoll, halt),
+              "CtlPoll mirrors a contiguous run of Ctl");
+constexpr size_t kHostMailBytes = 256;  // two CtlPoll slots
+static_assert(2 * sizeof(CtlPoll) <= kHostMailBytes, "mailbox holds two polls");
 
 // Constants of one solve, passed by value to the iteration kernels.
 struct SolveConst {

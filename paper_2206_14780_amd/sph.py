@@ -82,7 +82,8 @@ class sph_solve_report(C.Structure):
                 ("launches", C.c_int32), ("mat_nnz", C.c_int64), ("mat_slots", C.c_int64),
                 ("apply_ms", C.c_double), ("apply_launches", C.c_int32),
                 ("warm_used", C.c_int32 * 3), ("warm_rr", C.c_double * 3),
-                ("plain_rr", C.c_double * 3), ("warm_scale", C.c_double), ("warm_ms", C.c_double)]
+                ("plain_rr", C.c_double * 3), ("warm_scale", C.c_double), ("warm_ms", C.c_double),
+                ("issued_iters", C.c_int32)]
 
 
 _lib = None
@@ -328,7 +329,8 @@ class Context:
                    history_len=rep.history_len, mat_nnz=rep.mat_nnz, mat_slots=rep.mat_slots,
                    apply_ms=rep.apply_ms, apply_launches=rep.apply_launches,
                    warm_used=list(rep.warm_used), warm_rr=list(rep.warm_rr),
-                   plain_rr=list(rep.plain_rr), warm_scale=rep.warm_scale, warm_ms=rep.warm_ms)
+                   plain_rr=list(rep.plain_rr), warm_scale=rep.warm_scale, warm_ms=rep.warm_ms,
+                   issued_iters=rep.issued_iters)
         if history_cap > 0:
             out["history"] = [[hist[3 * i + c] for c in range(3)] for i in range(rep.history_len)]
         return out

@@ -260,6 +260,23 @@ def test_deterministic(ctx):
     assert np.array_equal(a, b) and ra["history"] == rb["history"]
 
 
+@pytest.mark.parametrize("poll_every", [1, 3, 16])
+def test_issue_batches_change_nothing_and_stop_near_the_halt(ctx, poll_every):
+    # How the host batches the iterations between its polls (and where it
+    # predicts the halt) changes nothing that the device computes; the
+    # predicted batches leave few iterations issued past the halt.
+    w = small_tank(seed=72, n=(16, 12, 10), dt_nu=80.0)
+    g = GpuCase(ctx, w)
+    a, ra = g.solve(w.rhs, S.SPH_F32, tol=1e-7)
+    b, rb = g.solve(w.rhs, S.SPH_F32, tol=1e-7, poll_every=poll_every)
+    assert ra["status"] == 0 and ra["iters"] >= 20
+    assert np.array_equal(a, b) and ra["history"] == rb["history"] and ra["iters"] == rb["iters"]
+    # each round of host-side residual checks issues its halting iteration
+    # (whose p-update decides the halt); beyond those, at most 3 are wasted
+    for r in (ra, rb):
+        assert r["iters"] <= r["issued_iters"] <= r["iters"] + r["n_true_checks"] + 3, r
+
+
 def test_restart_on_drop_matches_oracle_fp64(ctx):
     # The FP32 path's restart rule, exercised in FP64 so that GPU and oracle
     # take the same decisions: same restart count, same solution.
