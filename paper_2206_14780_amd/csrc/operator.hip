@@ -336,6 +336,7 @@ constexpr int kListCap = 96;                  // listed neighbours per row, Wend
 constexpr int kListCapGauss = 288;            // the same, truncated Gaussian
 constexpr size_t kListBudget = size_t(24) << 30;  // bytes of lists and weights at most
 constexpr int kBufStride = kChunk + 1;        // LDS words per lane (odd: no bank conflicts)
+constexpr int kFillGroup = 8;                 // list entries whose gathers are issued together
 static_assert(kListCap % kChunk == 0 && kListCapGauss % kChunk == 0, "whole segments");
 
 __device__ inline int64_t list_base(int64_t r, int32_t cap) {
@@ -446,10 +447,38 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
         if (f32) kahan_add(sum32, cmp32, (float)w);
         else sum += w;
     };
-    if (listed) {
+    if (listed && !f32) {
+        // groups of kFillGroup entries: indices, then positions and
+        // neighbour data loaded together, then the weights in list order
+        for (int32_t k0 = 0; k0 < c; k0 += kFillGroup) {
+            int32_t a[kFillGroup];
+#pragma unroll
+            for (int u = 0; u < kFillGroup; ++u) a[u] = k0 + u < c ? lst[list_off(k0 + u)] : row;
+            Pos4 pa[kFillGroup];
+            double2 ma[kFillGroup];
+#pragma unroll
+            for (int u = 0; u < kFillGroup; ++u) pa[u] = nv.pos[a[u]];
+            if (kind == kRowFluid) {
+#pragma unroll
+                for (int u = 0; u < kFillGroup; ++u) ma[u] = pv.mu_mr[a[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kFillGroup; ++u) {
+                if (k0 + u >= c) break;
+                const double dx = disp(pb.x, pa[u].x, g.period[0]);
+                const double dy = disp(pb.y, pa[u].y, g.period[1]);
+                const double dz = disp(pb.z, pa[u].z, g.period[2]);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                const double w = kind != kRowFluid ? pair_W(g, r2)
+                                                   : pair_w_v(g, op.avg, ma[u].x, ma[u].y, mu_b, ir_b, r2);
+                wl[(k0 + u) * kWave] = w;
+                add(w);
+            }
+        }
+    } else if (listed) {
         for (int32_t k = 0; k < c; ++k) {
             const int32_t a = lst[list_off(k)];
-            const double w = f32 ? weight32(a) : weight(a, dist2(a));
+            const double w = weight32(a);
             wl[k * kWave] = w;
             add(w);
         }
