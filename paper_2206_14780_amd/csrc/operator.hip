@@ -234,29 +234,46 @@ __global__ __launch_bounds__(kBlock) void k_slice_size(int64_t n, int64_t nslice
                                                        const int32_t* __restrict__ creal,
                                                        int64_t* __restrict__ size,
                                                        unsigned long long* __restrict__ nnz) {
-    // nnz[0]: nonzeros; the low 32 bits of nnz[1]: longest row (nonzeros)
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t w = 0, longest = 0;
+    // each wave takes slices in turn, lane l reading row 64 s + l; nnz[0]:
+    // nonzeros, the low 32 bits of nnz[1]: longest row (nonzeros), one
+    // atomic of each kind per block
+    __shared__ int64_t bt[kBlock / kWave];
+    __shared__ int32_t bl[kBlock / kWave];
+    const int lane = threadIdx.x % kWave;
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
     int64_t tot = 0;
-    if (s < nslices) {
-        for (int l = 0; l < kWave; ++l) {
-            int64_t r = s * kWave + l;
-            if (r < n) {
-                w = max(w, cnt[r]);
-                longest = max(longest, creal[r]);
-                tot += creal[r];
-            }
+    int32_t longest = 0;
+    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < nslices; s += (int64_t)gridDim.x * nw) {
+        const int64_t r = s * kWave + lane;
+        int32_t w = 0;
+        if (r < n) {
+            w = cnt[r];
+            const int32_t c = creal[r];
+            tot += c;
+            longest = max(longest, c);
         }
-        size[s] = (int64_t)((w + pack - 1) / pack * pack) * kWave;
+        for (int o = kWave / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kWave));
+        if (lane == 0) size[s] = (int64_t)((w + pack - 1) / pack * pack) * kWave;
     }
-    // one atomic of each kind per wave
     for (int o = kWave / 2; o > 0; o >>= 1) {
         tot += __shfl_xor(tot, o, kWave);
         longest = max(longest, __shfl_xor(longest, o, kWave));
     }
-    if ((threadIdx.x % kWave) == 0 && tot > 0) {
-        atomicAdd(nnz, (unsigned long long)tot);
-        atomicMax(reinterpret_cast<int32_t*>(nnz + 1), longest);
+    if (lane == 0) {
+        bt[wid] = tot;
+        bl[wid] = longest;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < nw; ++k) {
+            tot += bt[k];
+            longest = max(longest, bl[k]);
+        }
+        if (tot > 0) {
+            atomicAdd(nnz, (unsigned long long)tot);
+            atomicMax(reinterpret_cast<int32_t*>(nnz + 1), longest);
+        }
     }
 }
 
@@ -597,7 +614,8 @@ sph_status build_sell(sph_ctx* ctx, const sph_nbr* nb, const PartView& pv, const
         hipLaunchKernelGGL(k_row_scan, rows_grid, dim3(kBlock), 0, ctx->stream, nb->view(), pv, op, cnt, creal,
                            list, cap);
     }
-    hipLaunchKernelGGL(k_slice_size, dim3((unsigned)ceil_div(nslices, kBlock)), dim3(kBlock), 0, ctx->stream,
+    hipLaunchKernelGGL(k_slice_size, dim3((unsigned)std::min<int64_t>(ceil_div(nslices * kWave, kBlock), 1024)),
+                       dim3(kBlock), 0, ctx->stream,
                        n, nslices, (int32_t)pack_of<T>(), cnt, creal, size, nnz_dev);
     SPH_LAUNCHED("k_row_count/k_slice_size");
     SPH_TRY(scan_i64(ctx, size, ptr, nslices));
