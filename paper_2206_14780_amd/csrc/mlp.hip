@@ -1,6 +1,6 @@
 // Per-particle MLP that gives the solver its initial guess: forward,
-// backward and Adam on BF16 matrix cores (v_mfma_f32_16x16x16_bf16) with
-// FP32 accumulation.  Not part of the paper, which names better initial
+// backward and Adam on gfx950's BF16 matrix cores (v_mfma_f32_16x16x32_bf16)
+// with FP32 accumulation.  Not part of the paper, which names better initial
 // guesses as future work (Sections "Conclusions and future work" and
 // "Implementation notes").
 //
@@ -12,8 +12,14 @@
 // per tile.  Weights enter every product as BF16; the inputs of the 64x64
 // products (activations and gradient signals) are rounded to BF16 as well.
 //
-// MFMA 16x16x16 fragment layout (lane l, g = l / 16, c = l % 16, r = 0..3):
-//   A[c][4g + r],  B[4g + r][c],  D[4g + r][c].
+// MFMA fragment layout (lane l, g = l / 16, c = l % 16, r = 0..3): the
+// output D[4g + r][c]; the operands of one 16x16x32 step carry 8 values of K
+// per lane, A[c][k] and B[k][c] for the lane group's 8 slots.  The kernels
+// assign slot i of group g to K index 16 (i / 4) + 4 g + i % 4 of the step:
+// two 16-wide halves, each in the layout of a D output (rows 4g + r), so a
+// product's output (or two tiles' worth of samples) becomes the next
+// product's operand by concatenating two 4-value fragments, with no
+// shuffle.  A and B use the same assignment, so the product is exact in it.
 #include <algorithm>
 #include <cmath>
 
@@ -24,7 +30,18 @@ namespace sph {
 namespace mlp {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// The operand of one 16x16x32 step from two 4-value fragments (K slots
+// 0..3 and 4..7 of the lane group).
+__device__ inline bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 constexpr int kWaves = 4;             // waves per block
 constexpr int kThreads = kWaves * kWave;
@@ -108,14 +125,16 @@ __device__ inline void d_to_a(float* tile, const float (&v)[4][4], bf16x4 (&a)[4
     wave_sync();
 }
 
-// One 64x64 product on MFMA: out[t] (D layout) = A (16x64) x Wfrag.
+// One 64x64 product on MFMA: out[t] (D layout) = A (16x64) x Wfrag, two
+// 32-wide K steps (16-wide blocks 2s and 2s + 1).
 template <bool FWD>
 __device__ inline void mm64(const bf16x4 (&a)[4], const uint16_t* __restrict__ w, int g, int c, f32x4 (&acc)[4]) {
     for (int t = 0; t < 4; ++t) {
         acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < 4; ++s) {
-            const bf16x4 b = FWD ? bfrag_fwd(w, s, t, g, c) : bfrag_bwd(w, s, t, g, c);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b, acc[t], 0, 0, 0);
+        for (int s = 0; s < 2; ++s) {
+            const bf16x4 b0 = FWD ? bfrag_fwd(w, 2 * s, t, g, c) : bfrag_bwd(w, 2 * s, t, g, c);
+            const bf16x4 b1 = FWD ? bfrag_fwd(w, 2 * s + 1, t, g, c) : bfrag_bwd(w, 2 * s + 1, t, g, c);
+            acc[t] = mfma32(cat8(a[2 * s], a[2 * s + 1]), cat8(b0, b1), acc[t]);
         }
     }
 }
@@ -228,16 +247,23 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict_
         for (int k = 0; k < 4; ++k) sm.w4[i][k] = k < kOut ? rbf(p[kOW4 + i * kOut + k]) : 0.f;
     }
     if (threadIdx.x < 4) sm.b4[threadIdx.x] = threadIdx.x < kOut ? p[kOB4 + threadIdx.x] : 0.f;
-    // A operands: a[t][s] holds W[16s + 4g + r][16t + c] (W stored [in][out])
+    // A operands: step s of output tile t holds W[in][16t + c] (W stored
+    // [in][out]) for the lane group's K slots, in = 32s + 16 (i / 4) + 4g + i % 4
     const int lane = threadIdx.x % kWave, g = lane / 16, c = lane % 16;
-    bf16x4 a2[4][4], a3[4][4];
+    bf16x8 a2[4][2], a3[4][2];
     for (int t = 0; t < 4; ++t)
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 2; ++s) {
+            bf16x4 lo2, hi2, lo3, hi3;
             for (int r = 0; r < 4; ++r) {
-                const int in = 16 * s + 4 * g + r, o = 16 * t + c;
-                a2[t][s][r] = (short)f2bf(p[kOW2 + in * kH + o]);
-                a3[t][s][r] = (short)f2bf(p[kOW3 + in * kH + o]);
+                const int in = 32 * s + 4 * g + r, o = 16 * t + c;
+                lo2[r] = (short)f2bf(p[kOW2 + in * kH + o]);
+                hi2[r] = (short)f2bf(p[kOW2 + (in + 16) * kH + o]);
+                lo3[r] = (short)f2bf(p[kOW3 + in * kH + o]);
+                hi3[r] = (short)f2bf(p[kOW3 + (in + 16) * kH + o]);
             }
+            a2[t][s] = cat8(lo2, hi2);
+            a3[t][s] = cat8(lo3, hi3);
+        }
     __syncthreads();
     const int64_t ntiles = ceil_div(n, (int64_t)16);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
@@ -274,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict_
         f32x4 acc[4];
         for (int t = 0; t < 4; ++t) {
             acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[t][s], h[s], acc[t], 0, 0, 0);
+            for (int s = 0; s < 2; ++s) acc[t] = mfma32(a2[t][s], cat8(h[2 * s], h[2 * s + 1]), acc[t]);
         }
         for (int t = 0; t < 4; ++t) {
             const float4 b = *reinterpret_cast<const float4*>(&sm.b2[16 * t + 4 * g]);
@@ -286,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict_
         // lane's 16 features, then over the four lane groups of the sample
         for (int t = 0; t < 4; ++t) {
             acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[t][s], h[s], acc[t], 0, 0, 0);
+            for (int s = 0; s < 2; ++s) acc[t] = mfma32(a3[t][s], cat8(h[2 * s], h[2 * s + 1]), acc[t]);
         }
         float o0 = 0.f, o1 = 0.f, o2 = 0.f;
         for (int t = 0; t < 4; ++t) {
@@ -337,6 +363,23 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
         for (int j = 0; j < 4; ++j) gW2[i][j] = gW3[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float gW1[4][4] = {}, gb1[4] = {}, gb2[4] = {}, gb3[4] = {};
     float gW4[3] = {0.f, 0.f, 0.f}, gb4 = 0.f, sse = 0.f;
+    // The weight gradients h^T dz sum over the samples (K); one 32-wide
+    // step takes two tiles, so the operands of every even tile wait for the
+    // next tile (or for zeros after the last one).
+    bf16x4 pah3[4], pbz3[4], pah2[4], pbz2[4];
+    bool pend = false;
+    const auto wgrad = [&](f32x4 (&gW)[4][4], bf16x4 (&pa)[4], bf16x4 (&pb)[4], const bf16x4 (&ah)[4],
+                           const bf16x4 (&bz)[4]) {
+        if (!pend) {
+            for (int t = 0; t < 4; ++t) {
+                pa[t] = ah[t];
+                pb[t] = bz[t];
+            }
+            return;
+        }
+        for (int mt = 0; mt < 4; ++mt)
+            for (int nt = 0; nt < 4; ++nt) gW[mt][nt] = mfma32(cat8(pa[mt], ah[mt]), cat8(pb[nt], bz[nt]), gW[mt][nt]);
+    };
     for (int q = 0; q < tiles_per_wave; ++q) {
         const int64_t base = (gw * tiles_per_wave + q) * 16;
         Tile T;
@@ -389,9 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
                     ah[t][r] = (short)f2bf(T.h2[t][r]);
                     bz[t][r] = (short)f2bf(dz[t][r]);
                 }
-            for (int mt = 0; mt < 4; ++mt)
-                for (int nt = 0; nt < 4; ++nt)
-                    gW3[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mt], bz[nt], gW3[mt][nt], 0, 0, 0);
+            wgrad(gW3, pah3, pbz3, ah, bz);
         }
         bf16x4 a[4];
         d_to_a(tile, dz, a, g, c);
@@ -409,9 +450,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
                     ah[t][r] = (short)f2bf(T.h1[t][r]);
                     bz[t][r] = (short)f2bf(dz[t][r]);
                 }
-            for (int mt = 0; mt < 4; ++mt)
-                for (int nt = 0; nt < 4; ++nt)
-                    gW2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mt], bz[nt], gW2[mt][nt], 0, 0, 0);
+            wgrad(gW2, pah2, pbz2, ah, bz);
         }
         d_to_a(tile, dz, a, g, c);
         mm64<false>(a, sm.w2, g, c, acc);
@@ -422,6 +461,14 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
                 gb1[t] += d;
                 for (int f = 0; f < 4; ++f) gW1[f][t] = __builtin_fmaf(T.xD[r][f], d, gW1[f][t]);
             }
+        pend = !pend;
+    }
+    if (pend) {
+        // the last tile's weight gradients with a zero partner
+        const bf16x4 z4{0, 0, 0, 0};
+        const bf16x4 zero[4] = {z4, z4, z4, z4};
+        wgrad(gW3, pah3, pbz3, zero, zero);
+        wgrad(gW2, pah2, pbz2, zero, zero);
     }
     // write this wave's partial gradient
     float* P = part + gw * (int64_t)(kNParam + 1);
