@@ -372,8 +372,9 @@ typedef struct {
  *   p: positions, mass, rho, mu and type at step n (device, caller order).
  *   params: dt = the full step; wall, avg, jacobi, op_mode as for a solve.
  *   prec: SPH_F64 or SPH_MIXED (the velocities are FP64 arrays).
- *   opts: options of both solves (x0_given and the learned start are set by
- *         the step: each solve starts from the previous velocity).
+ *   opts: options of both solves; x0_given is set by the step (each solve
+ *         starts from the previous velocity: u^n, then u*), and a learned
+ *         start (warm_params) takes that velocity as its u (warm_u unused).
  *   pos_out[c]: device, n doubles: r^{n+1}; may be p->x, p->y, p->z.
  *   u[c]: device, n doubles: u^n on entry, u^{n+1} on exit.
  *   mu_out: device, n doubles: mu^{n+1} (a copy of p->mu without the

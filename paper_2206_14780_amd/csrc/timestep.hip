@@ -170,9 +170,10 @@ extern "C" sph_status sph_semi_implicit_step(sph_ctx* ctx, const sph_domain* dom
     double* un[3] = {buf + 10 * n, buf + 11 * n, buf + 12 * n};
     const dim3 grid((unsigned)ceil_div(n, (int64_t)kBlock)), block(kBlock);
 
+    // each solve starts from the previous velocity; a learned start
+    // (opts->warm_params) takes that velocity as its u
     sph_solve_opts o = *opts;
     o.x0_given = 1;
-    o.warm_params = nullptr;
     for (int c = 0; c < 3; ++c) o.warm_u[c] = nullptr;
     sph_solve_report rloc[2];
     sph_solve_report* rep = reports ? reports : rloc;

@@ -1,16 +1,26 @@
-"""Time steps of the non-Newtonian incline with the semi-implicit
-predictor/corrector of the library (sph_semi_implicit_step): per step a
-half-step solve, advection, neighbour rebuild, the Papanastasiou viscosity
-update from the new velocity, the full-step solve, and the corrector.
+"""Time steps with the semi-implicit predictor/corrector of the library
+(sph_semi_implicit_step): per step a half-step solve, advection, neighbour
+rebuild, the viscosity update (incline) from the new velocity, the
+full-step solve, and the corrector.
 
   python -m paper_2206_14780_amd.simulate --n 160 --steps 5
+  python -m paper_2206_14780_amd.simulate --workload lava --n 320 --steps 20 [--learned]
 
-The layer starts at rest with the viscosity of the workload's synthetic
-shear field; it is driven by the along-slope component of gravity (the
-normal component is carried by the pressure, which is outside this path).
+incline: the non-Newtonian layer starts at rest with the viscosity of the
+workload's synthetic shear field and is driven by the along-slope component
+of gravity (the normal component is carried by the pressure, which is
+outside this path); the Papanastasiou law updates the viscosity.
+lava: the lava-like channel as a Lagrangian sequence: from rest, driven along
+x, each particle keeping its own viscosity (its temperature moves with it);
+dt = the workload's (dt nu_max/dp^2 = 50) and the body force is
+`--g-scale` times the one of the frozen-position sequence (f = dt g =
+sin 10 deg), so that the fastest particle moves about a tenth of a particle
+spacing per step by the 20th step (the velocity is linear in g, the
+iteration counts are not affected by the scale); `--learned` starts both
+solves of every step from the learned guess.
 Prints one JSON line per step (wall time of the step call, iterations and
 device time of both solves, true relative residuals, velocity and viscosity
-ranges) and a summary line."""
+ranges, the largest displacement) and a summary line."""
 from __future__ import annotations
 
 import argparse
@@ -31,6 +41,9 @@ def main(argv=None):
     ap.add_argument("--prec", choices=("mixed", "f64"), default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--newtonian", action="store_true", help="keep the viscosity (no update)")
+    ap.add_argument("--workload", choices=("incline", "lava"), default="incline")
+    ap.add_argument("--g-scale", type=float, default=1e-8, help="lava: body force scale (see above)")
+    ap.add_argument("--learned", action="store_true", help="learned start in both solves of every step")
     a = ap.parse_args(argv)
 
     import torch
@@ -40,22 +53,34 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
 
+    from . import warmstart as WS
+
     tau0, m, mu0, slope = 100.0, 1000.0, 1.0, 10.0
     t0 = time.time()
-    w = W.incline_papanastasiou(a.n, tau0=tau0, m=m, mu0=mu0, slope_deg=slope, tol=a.tol)
+    if a.workload == "incline":
+        w = W.incline_papanastasiou(a.n, tau0=tau0, m=m, mu0=mu0, slope_deg=slope, tol=a.tol)
+        dt = a.dt_factor * w.dt
+        g = (math.sin(math.radians(slope)), 0.0, 0.0)
+        papa = None if a.newtonian else (tau0, m, mu0)
+    else:
+        w = W.lava_channel(a.n, tol=a.tol)
+        dt = w.dt
+        g = (a.g_scale * math.sin(math.radians(slope)) / w.dt, 0.0, 0.0)
+        papa = None
     log(f"[simulate] {w.name} n={w.n} generated in {time.time() - t0:.1f} s")
     ctx = S.Context(0)
     p = S.device_particles(w)
     dom = S.make_domain(w.lo, w.hi, w.periodic, w.h)
-    dt = a.dt_factor * w.dt
     par = S.make_params(dt, w.wall, w.avg, True, S.SPH_OP_CACHED)
     prec = S.SPH_MIXED if a.prec == "mixed" else S.SPH_F64
-    sp = S.make_step_params((math.sin(math.radians(slope)), 0.0, 0.0), None if a.newtonian else (tau0, m, mu0))
-    opts = S.make_opts(tol=a.tol)
+    sp = S.make_step_params(g, papa)
+    warm = torch.as_tensor(WS.load()).cuda() if a.learned else None
+    opts = S.make_opts(tol=a.tol, warm_params=warm)
     u = [torch.zeros(w.n, dtype=torch.float64, device="cuda") for _ in range(3)]
     fluid = torch.as_tensor(w.ptype == W.FLUID, device="cuda")
     rows = []
     for k in range(1, a.steps + 1):
+        x_before = p.x.clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         reps = ctx.sph_semi_implicit_step(dom, p, par, prec, sp, opts, [p.x, p.y, p.z], u, p.mu)
@@ -63,10 +88,18 @@ def main(argv=None):
         ms = (time.perf_counter() - t1) * 1e3
         rel = [max(float(np.sqrt(t / b)) for t, b in zip(r["true_rr"], r["bb"]) if b > 0) for r in reps]
         mu_f = p.mu[fluid]
+        dx = p.x - x_before
+        if w.periodic[0]:
+            per = float(w.hi[0] - w.lo[0])
+            dx = dx - per * torch.round(dx / per)
         row = dict(step=k, ms=round(ms, 2), iters=[r["iters"] for r in reps],
                    solve_ms=[round(r["setup_ms"] + r["iterate_ms"], 2) for r in reps],
                    status=[r["status"] for r in reps], true_rel_res=rel,
-                   max_ux=float(u[0].max()), mu_range=[float(mu_f.min()), float(mu_f.max())])
+                   max_ux=float(u[0].max()), max_dx=float(dx.abs().max()),
+                   mu_range=[float(mu_f.min()), float(mu_f.max())])
+        if a.learned:
+            row["learned_used"] = [r["warm_used"] for r in reps]
+            row["warm_ms"] = [round(r["warm_ms"], 2) for r in reps]
         rows.append(row)
         log(json.dumps(row))
         if any(r["status"] != S.SPH_OK for r in reps):
@@ -75,7 +108,8 @@ def main(argv=None):
     steady = rows[1:] if len(rows) > 1 else rows
     mean_ms = float(np.mean([r["ms"] for r in steady]))
     log(json.dumps(dict(summary=True, workload=w.name, n=int(w.n), steps=a.steps, dt=dt, prec=a.prec,
-                        tol=a.tol, viscosity_update=not a.newtonian, mean_step_ms=mean_ms,
+                        tol=a.tol, viscosity_update=papa is not None, learned=a.learned, mean_step_ms=mean_ms,
+                        total_solve_ms=float(sum(sum(r["solve_ms"]) for r in rows)),
                         mean_step_ms_excludes_first=len(rows) > 1,
                         solve_share=float(np.mean([sum(r["solve_ms"]) / r["ms"] for r in steady])),
                         particle_steps_per_s=w.n / (mean_ms * 1e-3),

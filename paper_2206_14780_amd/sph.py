@@ -349,7 +349,8 @@ class Context:
                                            C.byref(step), C.byref(opts), ps, us, _ptr(mu_out), reps)
         self._check(st, "sph_semi_implicit_step", soft_ok=True)
         return [dict(status=r.status, iters=r.iters, state=list(r.state), true_rr=list(r.true_rr),
-                     bb=list(r.bb), setup_ms=r.setup_ms, iterate_ms=r.iterate_ms) for r in reps]
+                     bb=list(r.bb), setup_ms=r.setup_ms, iterate_ms=r.iterate_ms,
+                     warm_used=list(r.warm_used), warm_ms=r.warm_ms) for r in reps]
 
 
     # --- learned initial guess ----------------------------------------------

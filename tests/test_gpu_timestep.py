@@ -137,6 +137,30 @@ def test_mixed_precision_step(ctx):
     assert np.abs(gp - pos).max() <= 1e-5 * dt * np.abs(uo).max() + 1e-12 * np.abs(pos).max()
 
 
+def test_step_with_learned_start(ctx):
+    # the learned start in both solves of a step: the same state as the
+    # plain step to the solves' tolerance
+    import torch
+    from paper_2206_14780_amd import warmstart as WS
+    w = W.incline_papanastasiou(n=10, seed=8)
+    dt = 100.0 * w.dt
+    u = _start(w, 5)
+    a = Run(ctx, w, u, prec=S.SPH_MIXED, tol=1e-9)
+    b = Run(ctx, w, u, prec=S.SPH_MIXED, tol=1e-9)
+    b.opts = S.make_opts(tol=1e-9, true_res_period=50, restart_drop=0.0,
+                         warm_params=torch.as_tensor(WS.load()).cuda())
+    ra, rb = a.step(dt), b.step(dt)
+    print(f"[step learned] iterations plain {[r['iters'] for r in ra]} learned {[r['iters'] for r in rb]}, "
+          f"components on the learned start {[r['warm_used'] for r in rb]}", flush=True)
+    assert all(r["status"] == 0 for r in ra + rb)
+    assert all(r["warm_used"] == [0, 0, 0] for r in ra)
+    pa, ua, ma = a.state()
+    pb, ub, mb = b.state()
+    assert rel_l2(ub, ua) < 1e-7
+    assert np.abs(pb - pa).max() <= 1e-7 * dt * np.abs(ua).max() + 1e-12 * np.abs(pa).max()
+    assert np.all(np.abs(mb - ma) <= 1e-6 * ma)
+
+
 def test_argument_checks(ctx):
     import torch
     w = W.incline_papanastasiou(n=6, seed=9)
