@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sph.h"
+#include "issue_plan.hpp"
 
 namespace sph {
 
@@ -170,17 +171,7 @@ struct Ctl {
     int32_t nonfinite;
 };
 
-// The fields of Ctl that the host polls between batches of iterations, in
-// one contiguous copy: residuals, tolerances, states, iteration and halt.
-struct CtlPoll {
-    double rr[3];
-    double bb[3];
-    double tau2[3];
-    int32_t state[3];
-    int32_t iter;
-    int32_t halt;
-    int32_t halt_reason;
-};
+// CtlPoll (issue_plan.hpp) mirrors a contiguous run of Ctl.
 static_assert(offsetof(Ctl, halt_reason) + sizeof(int32_t) - offsetof(Ctl, rr) == sizeof(CtlPoll) &&
                   offsetof(Ctl, state) - offsetof(Ctl, rr) == offsetof(CtlPoll, state) &&
                   offsetof(Ctl, halt) - offsetof(Ctl, rr) == offsetof(CtlPoll, halt),
