@@ -47,8 +47,8 @@ def _lattice_count(radius):
 @pytest.mark.parametrize("hf,key", [(1.3, "wendland"), (2.5, "wendland25")])
 def test_lattice_neighbour_count(hf, key):
     # Every interior particle of an unjittered cubic lattice has exactly the
-    # number of integer vectors v != 0 with |v| < 2 hf (the paper prints
-    # "around 80" for hf = 1.3 and "about twice" the Gaussian's 250 for 2.5).
+    # number of integer vectors v != 0 with |v| < 2 hf (the paper gives
+    # roughly 80 for hf = 1.3, and for 2.5 twice the Gaussian's count of 250).
     gold = json.load(open(os.path.join(GOLD, "kernel_neighbours.json")))
     expect = _lattice_count(2 * hf)
     if key == "wendland":
