@@ -257,10 +257,33 @@ __device__ inline double fma_t(double a, double b, double c) { return __builtin_
 // Reductions.  Every sum is taken in a fixed order that depends only on the
 // launch geometry, so repeated runs give bitwise identical scalars.
 // ---------------------------------------------------------------------------
+// A double moved across lanes by DPP (CTRL: a GFX9 DPP control word), both
+// halves; every source lane lies in the same row of 16, so none is masked.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double read_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS
+// traffic): a butterfly inside each row of 16 lanes (swap neighbours, swap
+// pairs, mirror the half rows, mirror the row), after which every lane of a
+// row holds the same row sum (each addition sees the same two operands in
+// both lanes), then the four row sums read from lanes 15, 31, 47 and 63 and
+// added as (R0 + R1) + (R2 + R3).  The result is the same in every lane.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 
 // Block-wide sum of K values per thread; result valid in every thread.
