@@ -43,11 +43,21 @@ __device__ inline double kernel_f(const Grid& g, double q) {
     return g.kernel == SPH_KERNEL_GAUSSIAN ? gauss_f(g, q) : wendland_f(q);
 }
 
-// Displacement on one axis, minimum image on periodic axes.  Rounded exactly
-// like the neighbour predicate everywhere in the library (contraction off).
+// Displacement on one axis, minimum image on periodic axes:
+// d - period * rint(d / period) with d = xb - xa, the same everywhere in the
+// library (contraction off), so that every path agrees on which pairs are
+// neighbours.  The quotient needs no division below one period: rounding is
+// monotonic, so |d| <= period/2 (exact in binary) gives |fl(d/period)| <= 1/2
+// and rint 0 (ties to even); period/2 < |d| < period gives a quotient above
+// 1/2 + 2^-54 (the next double above period/2 is at least that far), which
+// rounds above 1/2 and to at most 1, so rint gives sign(d) and the product
+// is exactly +-period.  Only |d| >= period takes the division.
 __device__ inline double disp(double xb, double xa, double period) {
     double d = xb - xa;
-    if (period > 0.0) d = d - period * rint(d / period);
+    if (period > 0.0) {
+        const double a = fabs(d);
+        if (a > 0.5 * period) d = a < period ? d - copysign(period, d) : d - period * rint(d / period);
+    }
     return d;
 }
 

@@ -73,6 +73,36 @@ def test_neighbours_tiny_and_clamped(ctx):
         assert np.array_equal(rp, orp) and np.array_equal(cols, ocols), w.name
 
 
+def test_neighbours_across_half_period(ctx):
+    # Separations of exactly half a period and a few ulps either side of it,
+    # with the support radius 2h equal to half the period: a separation one ulp
+    # above half a period is a neighbour only through its periodic image (one
+    # ulp below half a period), so the membership tests the minimum image at
+    # its wrap decision; half a period exactly is not (the quotient 1/2 rounds
+    # to 0, and 2h is excluded).  Lines along x and along y; periods of 1
+    # (a power of two) and 3.
+    for per in (1.0, 3.0):
+        half = 0.5 * per
+        offs = [0.0, half] + [half + s * k * np.spacing(half) for k in (1, 2, 3) for s in (1, -1)]
+        line = np.array(offs)
+        m = len(line)
+        px = np.stack([line, np.full(m, 0.1 * per), np.full(m, 0.2 * per)], axis=1)
+        py = np.stack([np.full(m, 0.6 * per), line, np.full(m, 0.7 * per)], axis=1)
+        pos = np.concatenate([px, py])
+        n = len(pos)
+        w = W.Workload(f"half_period_{per:g}", pos, np.ones(n), np.ones(n), np.ones(n),
+                       np.zeros(n, np.uint8), np.zeros(3), np.full(3, per), np.array([1, 1, 1]),
+                       0.25 * per, 0.1, 0, 0, np.ones((n, 3)), None, 1e-8)
+        print(f"[neighbours] {w.name} n={n}", flush=True)
+        g = GpuCase(ctx, w)
+        rp, cols = g.export()
+        orp, ocols = O.neighbors(w.pos, w.period, w.h, method="brute")
+        assert np.array_equal(rp, orp) and np.array_equal(cols, ocols), w.name
+        for base in (0, m):  # particle 0 of each line: +1 ulp wraps in, half a period does not
+            nb0 = set(ocols[orp[base]:orp[base + 1]].tolist())
+            assert base + 2 in nb0 and base + 1 not in nb0
+
+
 @pytest.mark.parametrize("prec", [S.SPH_F64, S.SPH_F32])
 @pytest.mark.parametrize("op_mode", [S.SPH_OP_CACHED, S.SPH_OP_ONTHEFLY])
 @pytest.mark.parametrize("jacobi", [True, False])
