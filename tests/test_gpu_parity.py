@@ -272,6 +272,17 @@ def test_single_particle(ctx):
         assert rep["status"] == 0 and np.array_equal(X, w.rhs)
 
 
+def test_empty_particle_set_rejected(ctx):
+    # a configuration holds at least one particle: an empty one is refused
+    # before any device work, and no handle is returned
+    w = W.Workload("empty", np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0, np.uint8),
+                   np.zeros(3), np.ones(3), np.array([0, 0, 0]), 0.1, 0.1, 0, 0, np.zeros((0, 3)), None, 1e-8)
+    parts = S.device_particles(w)
+    with pytest.raises(S.SphError) as e:
+        ctx.sph_build_neighbors(parts, S.make_domain(w.lo, w.hi, w.periodic, w.h))
+    assert e.value.status == S.SPH_E_ARG
+
+
 def test_true_residual_checks_match_oracle(ctx):
     w = small_tank(seed=61)
     g = GpuCase(ctx, w)
