@@ -108,7 +108,8 @@ __device__ inline void sell_group(const Sell<T>& A, int64_t base, int32_t width,
                 d[q * P + e] = pack_elem<uint16_t, P>(dv, e);
             }
             if constexpr (RES && sizeof(T) == 4) {
-                const typename Pack<float, P>::v lv = *reinterpret_cast<const typename Pack<float, P>::v*>(A.lo + i);
+                const typename Pack<float, P>::v lv =
+                    __builtin_nontemporal_load(reinterpret_cast<const typename Pack<float, P>::v*>(A.lo + i));
 #pragma unroll
                 for (int e = 0; e < P; ++e) l[q * P + e] = (double)pack_elem<float, P>(lv, e);
             } else {
