@@ -7,10 +7,11 @@
 // Network (one sample = one fluid particle and one velocity component):
 //   x[4] -> 64 -> 64 -> 64 -> o[3], ReLU on the hidden layers,
 //   pred = o0 B0 + o1 B1 + o2 B2 with basis B = (b_c, u_c, (u - A u)_c) / U.
-// The 4->64 and 64->3 layers run on the vector ALU; the two 64x64 layers,
-// their data gradients and their weight gradients run on MFMA, 16 samples
-// per tile.  Weights enter every product as BF16; the inputs of the 64x64
-// products (activations and gradient signals) are rounded to BF16 as well.
+// The two 64x64 layers, their data gradients and their weight gradients run
+// on MFMA, 16 samples per tile; the 4->64 and 64->3 layers run on the vector
+// ALU in FP32 in training and on MFMA with two-part BF16 inputs in inference.
+// Weights enter every product as BF16; the inputs of the 64x64 products
+// (activations and gradient signals) are rounded to BF16 as well.
 //
 // MFMA fragment layout (lane l, g = l / 16, c = l % 16, r = 0..3): the
 // output D[4g + r][c]; the operands of one 16x16x32 step carry 8 values of K
@@ -207,14 +208,22 @@ __device__ inline void load_tile(Tile& T, const float* __restrict__ S, const int
     }
 }
 
-// Inference: out[s] = (o0, o1, o2, pred) for samples [0, n).  The products
-// run transposed, Z^T = W^T H^T, with the 16 samples of a tile on the MFMA N
-// dimension: a product's output then sits in registers exactly as the next
-// product's B operand (lane (g, c) holds features 16t + 4g + r of sample c),
-// so no LDS transpose is needed, and the weights, as A operands, stay in
-// registers for the whole launch.  Same roundings as the training kernel's
-// forward pass (BF16 weights and layer inputs of the 64x64 products, FP32
-// layers 1 and 4); only the order of the FP32 sums differs.
+// Inference: out[s] = (o0, o1, o2, pred) for samples [0, n).  All four
+// products run on MFMA, transposed, Z^T = W^T H^T, with the 16 samples of a
+// tile on the MFMA N dimension: a product's output then sits in registers
+// exactly as the next product's B operand (lane (g, c) holds features
+// 16t + 4g + r of sample c), so no LDS transpose is needed; the weights of
+// the 64x64 layers, as A operands, stay in registers for the whole launch,
+// those of the first and last layers in LDS.  The 64x64 layers take BF16
+// weights and BF16 layer inputs, as in the training kernel.  The first and
+// last layers take their inputs as sums of BF16 parts against the same BF16
+// weight: the features as three parts, which hold an FP32 value exactly (K
+// slots 4g + r, g = 0, 1, 2, carry part g of feature r), so layer 1 equals
+// the training kernel's FP32 layer up to the order of its FP32 sums (its
+// output is rounded to BF16 next, where a less accurate input would flip
+// roundings); the last hidden layer as two parts, to 2^-16 relative (one K
+// step per part; the output is not rounded again).  The training kernel
+// evaluates these two layers in FP32 on the vector ALU.
 // Two floats to packed BF16, nearest-even (the hardware conversion of
 // gfx950; the same rounding as f2bf on finite values).
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -226,25 +235,33 @@ __device__ inline uint32_t pk_bf16(float lo, float hi) {
 __device__ inline bf16x4 bf16x4_of(float v0, float v1, float v2, float v3) {
     return __builtin_bit_cast(bf16x4, u32x2{pk_bf16(v0, v1), pk_bf16(v2, v3)});
 }
+// The four values' BF16 parts: hi = nearest BF16, lo = BF16 of v - hi (the
+// remainder v - hi is exact in FP32); rem receives v - hi - lo, exact too.
+__device__ inline void bf16x4_split(const float (&v)[4], bf16x4& hi, bf16x4& lo, float (&rem)[4]) {
+    hi = bf16x4_of(v[0], v[1], v[2], v[3]);
+    for (int r = 0; r < 4; ++r) rem[r] = v[r] - bf2f((uint16_t)hi[r]);
+    lo = bf16x4_of(rem[0], rem[1], rem[2], rem[3]);
+    for (int r = 0; r < 4; ++r) rem[r] -= bf2f((uint16_t)lo[r]);
+}
 
 struct alignas(16) InferSmem {
-    alignas(16) float w1[kIn][kH];  // BF16-rounded values
     alignas(16) float b1[kH];
     alignas(16) float b2[kH];
     alignas(16) float b3[kH];
-    alignas(16) float w4[kH][4];    // BF16-rounded values, padded to 4
     alignas(16) float b4[4];
+    alignas(16) bf16x8 a1[4][kWave];  // A operands of layer 1 (tile t, lane)
+    alignas(16) bf16x8 a4[2][kWave];  // A operands of layer 4 (K step s, lane)
 };
 
-__global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict__ S, int64_t n,
+// At most 128 registers, so that four waves share a SIMD (the operands' set-up
+// spills a few values once per block, none in the tile loop).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_infer(const float* __restrict__ S, int64_t n,
                                                         const float* __restrict__ p, float* __restrict__ out) {
     __shared__ __align__(16) InferSmem sm;
-    for (int i = threadIdx.x; i < kIn * kH; i += blockDim.x) sm.w1[i / kH][i % kH] = rbf(p[kOW1 + i]);
     for (int i = threadIdx.x; i < kH; i += blockDim.x) {
         sm.b1[i] = p[kOB1 + i];
         sm.b2[i] = p[kOB2 + i];
         sm.b3[i] = p[kOB3 + i];
-        for (int k = 0; k < 4; ++k) sm.w4[i][k] = k < kOut ? rbf(p[kOW4 + i * kOut + k]) : 0.f;
     }
     if (threadIdx.x < 4) sm.b4[threadIdx.x] = threadIdx.x < kOut ? p[kOB4 + threadIdx.x] : 0.f;
     // A operands: step s of output tile t holds W[in][16t + c] (W stored
@@ -264,37 +281,51 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict_
             a2[t][s] = cat8(lo2, hi2);
             a3[t][s] = cat8(lo3, hi3);
         }
+    // layer 1: K slot 4g + r (g = 0, 1, 2: the three parts) is feature r;
+    // the other slots are zero.  Layer 4: output row c (< 3) of
+    // W4^T, K = the 64 hidden units.  Both kept in LDS (one copy per lane
+    // index, shared by the block's waves), read once per tile.
+    const bf16x4 z4 = {0, 0, 0, 0};
+    if (threadIdx.x < kWave) {
+        for (int t = 0; t < 4; ++t) {
+            bf16x4 w = z4;
+            if (g < 3)
+                for (int r = 0; r < 4; ++r) w[r] = (short)f2bf(p[kOW1 + r * kH + 16 * t + c]);
+            sm.a1[t][lane] = cat8(w, z4);
+        }
+        for (int s = 0; s < 2; ++s) {
+            bf16x4 lo4 = z4, hi4 = z4;
+            if (c < kOut)
+                for (int r = 0; r < 4; ++r) {
+                    const int in = 32 * s + 4 * g + r;
+                    lo4[r] = (short)f2bf(p[kOW4 + in * kOut + c]);
+                    hi4[r] = (short)f2bf(p[kOW4 + (in + 16) * kOut + c]);
+                }
+            sm.a4[s][lane] = cat8(lo4, hi4);
+        }
+    }
     __syncthreads();
     const int64_t ntiles = ceil_div(n, (int64_t)16);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     for (int64_t tile = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; tile < ntiles; tile += nw) {
         // re-read the small LDS tables every tile rather than keeping them
-        // in registers (which would leave room for one wave per SIMD)
+        // in registers (which would leave room for fewer waves per SIMD)
         __asm__ volatile("" ::: "memory");
         const int64_t smp = tile * 16 + c;
         const bool valid = smp < n;
         const float4 x = valid ? *reinterpret_cast<const float4*>(S + smp * kSample) : float4{0.f, 0.f, 0.f, 0.f};
-        // layer 1 (FP32), ReLU, BF16: the B operand of layer 2
+        // layer 1 on MFMA, bias, ReLU, BF16: the B operand of layer 2
+        bf16x4 xh, xm;
+        float xr[4];
+        bf16x4_split({x.x, x.y, x.z, x.w}, xh, xm, xr);
+        const bf16x4 xl = bf16x4_of(xr[0], xr[1], xr[2], xr[3]);  // exact: at most 8 bits remain
+        const bf16x8 b1 = cat8(g == 0 ? xh : (g == 1 ? xm : (g == 2 ? xl : z4)), z4);
         bf16x4 h[4];
-        for (int s = 0; s < 4; ++s) {
-            const int j = 16 * s + 4 * g;
-            const float4 b = *reinterpret_cast<const float4*>(&sm.b1[j]);
-            const float4 w0 = *reinterpret_cast<const float4*>(&sm.w1[0][j]);
-            const float4 w1 = *reinterpret_cast<const float4*>(&sm.w1[1][j]);
-            const float4 w2 = *reinterpret_cast<const float4*>(&sm.w1[2][j]);
-            const float4 w3 = *reinterpret_cast<const float4*>(&sm.w1[3][j]);
-            const float bb[4] = {b.x, b.y, b.z, b.w};
-            const float c0[4] = {w0.x, w0.y, w0.z, w0.w}, c1[4] = {w1.x, w1.y, w1.z, w1.w};
-            const float c2[4] = {w2.x, w2.y, w2.z, w2.w}, c3[4] = {w3.x, w3.y, w3.z, w3.w};
-            float z[4];
-            for (int r = 0; r < 4; ++r) {
-                z[r] = bb[r];
-                z[r] = __builtin_fmaf(x.x, c0[r], z[r]);
-                z[r] = __builtin_fmaf(x.y, c1[r], z[r]);
-                z[r] = __builtin_fmaf(x.z, c2[r], z[r]);
-                z[r] = __builtin_fmaf(x.w, c3[r], z[r]);
-            }
-            h[s] = bf16x4_of(fmaxf(z[0], 0.f), fmaxf(z[1], 0.f), fmaxf(z[2], 0.f), fmaxf(z[3], 0.f));
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 z = mfma32(sm.a1[t][lane], b1, f32x4{0.f, 0.f, 0.f, 0.f});
+            const float4 b = *reinterpret_cast<const float4*>(&sm.b1[16 * t + 4 * g]);
+            h[t] = bf16x4_of(fmaxf(z[0] + b.x, 0.f), fmaxf(z[1] + b.y, 0.f), fmaxf(z[2] + b.z, 0.f),
+                             fmaxf(z[3] + b.w, 0.f));
         }
         // layer 2 on MFMA, bias, ReLU, BF16: the B operand of layer 3
         f32x4 acc[4];
@@ -308,34 +339,29 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(const float* __restrict_
             h[t] = bf16x4_of(fmaxf(acc[t][0] + bb[0], 0.f), fmaxf(acc[t][1] + bb[1], 0.f),
                              fmaxf(acc[t][2] + bb[2], 0.f), fmaxf(acc[t][3] + bb[3], 0.f));
         }
-        // layer 3 on MFMA, bias, ReLU; layer 4 (FP32) partial sums over this
-        // lane's 16 features, then over the four lane groups of the sample
+        // layer 3 on MFMA, bias, ReLU, split into BF16 parts: the B operands
+        // of layer 4
         for (int t = 0; t < 4; ++t) {
             acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int s = 0; s < 2; ++s) acc[t] = mfma32(a3[t][s], cat8(h[2 * s], h[2 * s + 1]), acc[t]);
         }
-        float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+        bf16x4 hh[4], hl[4];
         for (int t = 0; t < 4; ++t) {
             const float4 b = *reinterpret_cast<const float4*>(&sm.b3[16 * t + 4 * g]);
-            const float bb[4] = {b.x, b.y, b.z, b.w};
-            for (int r = 0; r < 4; ++r) {
-                const float v = fmaxf(acc[t][r] + bb[r], 0.f);
-                const float4 w = *reinterpret_cast<const float4*>(&sm.w4[16 * t + 4 * g + r][0]);
-                o0 = __builtin_fmaf(v, w.x, o0);
-                o1 = __builtin_fmaf(v, w.y, o1);
-                o2 = __builtin_fmaf(v, w.z, o2);
-            }
+            const float v[4] = {fmaxf(acc[t][0] + b.x, 0.f), fmaxf(acc[t][1] + b.y, 0.f),
+                                fmaxf(acc[t][2] + b.z, 0.f), fmaxf(acc[t][3] + b.w, 0.f)};
+            float rem[4];
+            bf16x4_split(v, hh[t], hl[t], rem);
         }
-        o0 += __shfl_xor(o0, 16, kWave);
-        o1 += __shfl_xor(o1, 16, kWave);
-        o2 += __shfl_xor(o2, 16, kWave);
-        o0 += __shfl_xor(o0, 32, kWave);
-        o1 += __shfl_xor(o1, 32, kWave);
-        o2 += __shfl_xor(o2, 32, kWave);
+        // layer 4 on MFMA: rows 0-2 of the output tile (lanes of group 0)
+        f32x4 o4 = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < 2; ++s) {
+            const bf16x8 w4 = sm.a4[s][lane];
+            o4 = mfma32(w4, cat8(hh[2 * s], hh[2 * s + 1]), o4);
+            o4 = mfma32(w4, cat8(hl[2 * s], hl[2 * s + 1]), o4);
+        }
         if (g == 0 && valid) {
-            o0 += sm.b4[0];
-            o1 += sm.b4[1];
-            o2 += sm.b4[2];
+            const float o0 = o4[0] + sm.b4[0], o1 = o4[1] + sm.b4[1], o2 = o4[2] + sm.b4[2];
             const float4 bs = *reinterpret_cast<const float4*>(S + smp * kSample + 4);
             float pred = o0 * bs.x;
             pred = __builtin_fmaf(o1, bs.y, pred);
