@@ -90,3 +90,19 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "--gpus 2" in r.stderr and r.stdout == ""
+
+
+def test_traffic_summary_is_machine_readable():
+    # bench.py reads the dominant kernel's measured HBM bytes per launch from
+    # the committed counter summary, and reports them only while the listed
+    # kernel sources hash to the recorded value: the three fields are there,
+    # the byte count is a positive integer, and every listed source exists
+    import bench
+    txt = open(bench.TRAFFIC_PROFILE).read()
+    fields = dict(l.split(": ", 1) for l in txt.splitlines()
+                  if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "source_files:")))
+    assert set(fields) == {"traffic_bytes_per_launch", "source_sha256", "source_files"}
+    assert int(fields["traffic_bytes_per_launch"]) > 0
+    assert len(fields["source_sha256"].strip()) == 64
+    files = fields["source_files"].split()
+    assert files and all(os.path.exists(os.path.join(ROOT, f)) for f in files)
