@@ -1194,7 +1194,7 @@ int orc_cg(const orc_op *op, const double *const *b, double *const *x, double to
         if (!any_prog || it >= max_iter) break;
         ++it;
         int stall[3] = {0, 0, 0};
-        /* p_i = r_i + beta_i p_{i-1} */
+        /* direction update (beta = 0: the direction restarts from r) */
         for (int c = 0; c < 3; ++c) {
             double bt = beta[c];
             double *pc = p[c];
