@@ -530,15 +530,30 @@ __global__ __launch_bounds__(kThreads) void k_mlp_train(const float* __restrict_
 // Sums the per-wave partials in a fixed order.  With Adam (step > 0) it
 // updates the FP32 master weights (Kingma & Ba, bias-corrected); otherwise it
 // writes the gradient to `grad`.  out[0] = mean squared error of the batch.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ part, int32_t nparts,
-                                                    int64_t batch, float* __restrict__ params,
-                                                    float* __restrict__ m, float* __restrict__ v,
-                                                    float* __restrict__ grad, int32_t step, double lr,
-                                                    double* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > kNParam) return;
+// Sums the per-wave partials of every parameter (and of the loss) in FP64
+// and applies Adam.  One lane per parameter, kRedWaves waves per block: wave
+// w adds the partials w, w + kRedWaves, ... in that order, then the first
+// wave adds the waves' sums in wave order, so the result depends only on
+// the number of partials, not on timing.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(kRedWaves * kWave) void k_mlp_reduce(const float* __restrict__ part, int32_t nparts,
+                                                                  int64_t batch, float* __restrict__ params,
+                                                                  float* __restrict__ m, float* __restrict__ v,
+                                                                  float* __restrict__ grad, int32_t step,
+                                                                  double lr, double* __restrict__ out) {
+    __shared__ double lds[kRedWaves][kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int p = blockIdx.x * kWave + lane;
+    double sw = 0.0;
+    if (p <= kNParam) {
+#pragma unroll 8
+        for (int q = w; q < nparts; q += kRedWaves) sw += (double)part[(int64_t)q * (kNParam + 1) + p];
+    }
+    lds[w][lane] = sw;
+    __syncthreads();
+    if (w != 0 || p > kNParam) return;
     double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += (double)part[(int64_t)w * (kNParam + 1) + p];
+    for (int k = 0; k < kRedWaves; ++k) s += lds[k][lane];
     if (p == kNParam) {
         out[0] = s / (double)batch;
         return;
@@ -603,7 +618,8 @@ static sph_status train_or_grad(sph_ctx* ctx, const float* samples, const int32_
     SPH_TRY(ctx->ensure_t(kMlpOut, 1, &out));
     hipLaunchKernelGGL(k_mlp_train, dim3(grid), dim3(kThreads), 0, ctx->stream, samples, idx, batch, params, part,
                        tpw);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)ceil_div(kNParam + 1, 256)), dim3(256), 0, ctx->stream, part,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)ceil_div(kNParam + 1, kWave)), dim3(kRedWaves * kWave), 0,
+                       ctx->stream, part,
                        (int32_t)nparts, batch, params, m, v, grad, step, lr, out);
     SPH_LAUNCHED("k_mlp_train/k_mlp_reduce");
     if (loss) {
