@@ -444,14 +444,6 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
         return (double)pair_w_f32(g, op.avg, (float)pv.mu[a], (float)pv.mass[a], (float)pv.rho[a], mub32, rhob32,
                                   r2);
     };
-    // r^2 exactly as the scan computes it
-    const auto dist2 = [&](int32_t a) {
-        const Pos4 pa = nv.pos[a];
-        double dx = disp(pb.x, pa.x, g.period[0]);
-        double dy = disp(pb.y, pa.y, g.period[1]);
-        double dz = disp(pb.z, pa.z, g.period[2]);
-        return (dx * dx + dy * dy) + dz * dz;
-    };
     const auto scan = [&](auto&& f) {  // unlisted rows: the scan again
         for_each_neighbor(nv, row, [&](int32_t a, double r2) {
             if (kind == kRowDummy && pv.type[a] != SPH_FLUID) return;
@@ -482,6 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fill_list(NbrView nv, PartView p
 #pragma unroll
             for (int u = 0; u < kFillGroup; ++u) {
                 if (k0 + u >= c) break;
+                // r^2 exactly as the scan computes it
                 const double dx = disp(pb.x, pa[u].x, g.period[0]);
                 const double dy = disp(pb.y, pa[u].y, g.period[1]);
                 const double dz = disp(pb.z, pa[u].z, g.period[2]);
